@@ -1,0 +1,197 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D3Q19 LBM-LES library (liblbm.so).
+ *
+ * The library advances the weakly compressible lattice-Boltzmann model of
+ * arXiv 2607.04516, Appendix D ("Lattice Boltzmann method in FluidX3D"):
+ * D3Q19 velocities, second-order Hermite equilibrium (eq. D.4), single
+ * relaxation time BGK collision (eq. D.2) with the Smagorinsky-Lilly eddy
+ * viscosity obtained locally from the non-equilibrium momentum flux
+ * (eqs. D.7-D.11), streaming (eq. D.3) with halfway bounce-back at solid
+ * cells and at wall faces (App. D, last paragraph), and equilibrium-velocity
+ * inflow cells (Sec. 3, boundary conditions).  Zero-gradient outflow,
+ * free-slip and periodic faces complete the face set.  An optional uniform
+ * body force enters through Guo's forcing scheme (the scheme App. E names).
+ *
+ * Conventions for every entry point
+ *  - Return value: LBM_OK (0) or a negative LBM_E* code; no exception or
+ *    longjmp crosses the ABI.  lbm_last_error() gives the message.
+ *  - Cell order: n = x + nx*(y + ny*z), x fastest.  "Canonical" population
+ *    arrays are [19][nz][ny][nx] in the direction order below, holding the
+ *    shifted pre-collision populations h_i = f_i - w_i*rho0 of time t.
+ *  - Direction order: 0 rest; 1/2 = +-x; 3/4 = +-y; 5/6 = +-z; 7/8 = +-(1,1,0);
+ *    9/10 = +-(1,0,1); 11/12 = +-(0,1,1); 13/14 = +-(1,-1,0);
+ *    15/16 = +-(1,0,-1); 17/18 = +-(0,1,-1).  Weights 1/3, 1/18, 1/36.
+ *  - Element type of device arrays: "real" is double for an LBM_F64 context
+ *    and float otherwise; "store" is the storage type of the context
+ *    (double, float, IEEE binary16, bfloat16).
+ *  - Host pointers are read during the call and copied; device pointers are
+ *    borrowed for the duration of the enqueued work only.  The context owns
+ *    every allocation it makes (populations, mask bits, ghost planes,
+ *    reduction scratch) and frees them in lbm_destroy().
+ *  - All work is enqueued on the context's HIP stream (params.hip_stream,
+ *    or the null stream).  Only lbm_probe, lbm_mass and lbm_step with the
+ *    watchdog on synchronise with the host.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* bad dimensions, tau0 <= 1/2, unpaired periodic face, null pointer */
+#define LBM_ENOMEM (-2)    /* device allocation failed */
+#define LBM_EHIP (-3)      /* HIP runtime error; text in lbm_last_error() */
+#define LBM_EUNSTABLE (-4) /* watchdog: NaN/Inf, |u| > 0.5 or |rho - rho0| > 0.5 somewhere */
+#define LBM_ESTATE (-5)    /* call out of order, e.g. stepping with an inflow face lacking a profile */
+
+enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
+
+enum lbm_face_kind {
+    LBM_PERIODIC = 0,   /* wraps to the opposite face; both faces of the axis must be periodic */
+    LBM_INFLOW_EQ = 1,  /* the face layer holds feq(rho0, u_in(z)) cells */
+    LBM_OUTFLOW_ZG = 2, /* zero-gradient: entering populations copy the inner layer */
+    LBM_FREESLIP = 3,   /* specular reflection at the half plane outside the face */
+    LBM_WALL = 4        /* halfway bounce-back at the half plane outside the face */
+};
+
+enum lbm_face { LBM_XM = 0, LBM_XP = 1, LBM_YM = 2, LBM_YP = 3, LBM_ZM = 4, LBM_ZP = 5 };
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz; /* each >= 3 */
+} lbm_grid;
+
+typedef struct {
+    double tau0;          /* molecular relaxation time, > 1/2 (eq. D.5: nu0 = (tau0 - 1/2)/3) */
+    double c_smag;        /* Smagorinsky constant C (eq. D.7); 0 disables the closure */
+    double delta;         /* filter width Delta in lattice units (eq. D.7) */
+    double rho0;          /* reference density; inflow cells hold feq(rho0, u_in) */
+    double body_force[3]; /* uniform force per unit volume, Guo scheme */
+    double u_init[3];     /* uniform initial velocity used by lbm_create */
+    double noise_amp;     /* initial noise: u += amp*(2*U - 1), U from splitmix64 */
+    uint64_t noise_seed;  /* U for component c of cell n = splitmix64(seed + 3n + c) >> 11 * 2^-53 */
+    int32_t storage;      /* enum lbm_storage */
+    int32_t face[6];      /* enum lbm_face_kind per face, order x-, x+, y-, y+, z-, z+ */
+    int32_t watchdog_stride; /* check for blow-up every this many steps; 0 = off */
+    void *hip_stream;     /* hipStream_t borrowed from the caller; NULL = null stream */
+} lbm_params;
+
+/* Create a context.  solid: host uint8 [nz][ny][nx], nonzero = solid cell
+ * (buildings and terrain voxels, Sec. 2.1); copied and bit-packed on the
+ * device.  Allocates the population array (19 * nx_pitch * ny * nz * sizeof(store))
+ * and initialises the state at t = 0 to feq(rho0, u_init + noise) in fluid
+ * cells and h = 0 in solid cells.  Errors: EINVAL, ENOMEM, EHIP; *out is
+ * NULL on error and lbm_last_error(NULL) gives the message. */
+int lbm_create(const lbm_grid *grid, const uint8_t *solid, const lbm_params *params, lbm_ctx **out);
+
+/* Set the velocity profile of an INFLOW_EQ face: host double [nz][3]; a cell
+ * of the face layer at height z takes feq(rho0, u[z]) (Sec. 3: equilibrium
+ * velocity boundaries; App. F: the boundary velocity array).  A cell on two
+ * inflow faces takes the profile of the lower-numbered face.  Takes effect at
+ * the next step.  Errors: EINVAL (face not INFLOW_EQ, NULL u). */
+int lbm_set_inflow(lbm_ctx *ctx, int32_t face, const double *u);
+
+/* Re-initialise the state at t = 0 to feq(rho0, u0[z] + noise) in fluid
+ * cells.  u0: host double [nz][3], or NULL for params.u_init. */
+int lbm_reset(lbm_ctx *ctx, const double *u0);
+
+/* Advance n >= 0 steps of collide-and-stream (eqs. D.2, D.3 with D.4, D.11).
+ * Asynchronous unless the watchdog fires inside the n steps (then it
+ * synchronises and returns EUNSTABLE with the state at the failing check).
+ * Errors: ESTATE (an inflow face has no profile), EUNSTABLE, EHIP. */
+int lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* As lbm_step, and after every step adds u(x_p, t+1) of each registered
+ * probe cell (lbm_set_probes) to acc: device real [np][3]. */
+int lbm_step_probed(lbm_ctx *ctx, int64_t n, void *acc);
+
+/* Macroscopic fields of the current state (eq. D.1; nu_t from eqs. D.6, D.11
+ * as (tau_eff - tau0)/3, the value the next collision uses).  Device real
+ * arrays rho [N], u [3][N], nu_t [N], N = nx*ny*nz; any may be NULL.  Inflow
+ * cells report (rho0, u_in, 0), solid cells (rho0, 0, 0). */
+int lbm_macros(lbm_ctx *ctx, void *rho, void *u, void *nu_t);
+
+/* Sample rho and u at np points: pts host float [np][3] in lattice
+ * coordinates (cell centres at integers); out host float [np][4] =
+ * (rho, ux, uy, uz).  Integer points return that cell; other points are
+ * trilinear in the cell values (solid cells count as rho0, u = 0); points
+ * outside [0, n-1] are clamped.  Synchronises. */
+int lbm_probe(lbm_ctx *ctx, const float *pts, int32_t np, float *out);
+
+/* Mass sum(rho) and kinetic energy sum(rho |u|^2 / 2) over fluid cells
+ * (solid and inflow cells excluded).  Per-lane compensated sums of
+ * rho - rho0 in real precision, then a deterministic double-precision tree
+ * over lanes and blocks.  Synchronises. */
+int lbm_mass(lbm_ctx *ctx, double *mass, double *kinetic_energy);
+
+/* Export the canonical state of time t (see conventions) into dst: device
+ * store [19][N].  Inflow cells hold h_eq(rho0, u_in), solid cells 0. */
+int lbm_get_state(lbm_ctx *ctx, void *dst, int64_t *t);
+
+/* Import a canonical state (device store [19][N]) as time t.  Values of
+ * solid and inflow cells are ignored. */
+int lbm_set_state(lbm_ctx *ctx, const void *src, int64_t t);
+
+/* Register integer probe cells: host int32 [np][3] = (x, y, z), each a
+ * non-solid cell inside the grid; np <= 4096.  Used by lbm_step_probed,
+ * lbm_probe_accumulate and lbm_adjoint_step. */
+int lbm_set_probes(lbm_ctx *ctx, const int32_t *cells, int32_t np);
+
+/* acc (device real [np][3]) += u of the registered probe cells in the
+ * current state. */
+int lbm_probe_accumulate(lbm_ctx *ctx, void *acc);
+
+/* Time statistics: while set, every step from a time t with t % stride == 0
+ * adds u(t) and u(t)^2 into acc (device real [6][N]: sum ux, uy, uz, then
+ * sum ux^2, uy^2, uz^2) inside the step kernel.  acc NULL or stride <= 0
+ * turns the statistics off. */
+int lbm_set_stats(lbm_ctx *ctx, void *acc, int32_t stride);
+
+/* One step from a canonical state to a canonical state, out of place:
+ * src, dst device store [19][N], distinct.  Uses the context's geometry,
+ * parameters and inflow profiles; does not touch its state or time.  This is
+ * the recompute step of the checkpointed adjoint. */
+int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
+
+/* One discrete-adjoint step (transpose of the linearised update, eqs. D.2-D.4
+ * and D.11 differentiated by hand):
+ *   lam = J_C(f_t)^T S^T lam_next + d(loss)/d f(t),
+ * where S is the streaming with its boundary rules and J_C the Jacobian of
+ * the local collision at the canonical state f_t (device store [19][N]).
+ * lam_next, lam: device real [19][N] canonical layout, distinct.
+ * probe_src: device real [np][3] = dL/du(x_p, t) for the registered probes,
+ * or NULL.  g_inflow: device real [2][6][nz][3]; [0] += the gradient of the
+ * loss with respect to each inflow face profile u_in(face, z) through the
+ * step t -> t+1, as a compensated (Neumaier) sum with [1] the compensation.
+ * Solid and inflow cells get lam = 0. */
+int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
+                     const void *probe_src, void *g_inflow);
+
+/* Current time step t of the context's state. */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/* Number of fluid cells (non-solid, including inflow cells) and of the
+ * cells counted by lbm_mass (non-solid, non-inflow). */
+int lbm_cell_counts(const lbm_ctx *ctx, int64_t *fluid, int64_t *interior);
+
+/* Replace the HIP stream work is enqueued on (NULL = null stream). */
+int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
+
+/* Message of the last error of ctx (ctx-owned string), or of the last
+ * failed lbm_create on this thread when ctx is NULL. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Free every allocation of the context (synchronises its stream). */
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,203 @@
+"""Double-precision CPU oracle for the D3Q19 BGK + Smagorinsky update.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package; the HIP library
+never does.  It wraps ``lbm_oracle.c`` (plain C loops, FP64, two lattices with
+pull streaming) through ctypes and shares no code with the HIP path.
+
+Arrays follow the oracle's own conventions: populations are unshifted ``f`` of
+shape ``[19, nz, ny, nx]`` (float64), the solid mask is ``[nz, ny, nx]`` uint8,
+inflow profiles are ``[6, nz, 3]`` float64 (face order x-, x+, y-, y+, z-, z+).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "lbm_oracle.c"), os.path.join(_HERE, "lbm_oracle_adjoint.c")]
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+PERIODIC, INFLOW_EQ, OUTFLOW_ZG, FREESLIP, WALL = 0, 1, 2, 3, 4
+NQ = 19
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (strict IEEE: no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        srcs = [s for s in _SRC if os.path.exists(s)]
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-o", _LIB + ".tmp", *srcs, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("face", ctypes.c_int32 * 6),
+                ("tau0", ctypes.c_double), ("c_smag", ctypes.c_double),
+                ("delta", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("force", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.or_lattice.argtypes = [P, P, P]
+        lib.or_equilibrium.argtypes = [ctypes.c_double, P, P]
+        lib.or_moments.argtypes = [P, P, P, P]
+        lib.or_tau_eff.argtypes = [ctypes.c_double] * 5
+        lib.or_tau_eff.restype = ctypes.c_double
+        lib.or_q_invariant.argtypes = [P, P, P]
+        lib.or_q_invariant.restype = ctypes.c_double
+        lib.or_collide.argtypes = [P, P, P, P, P]
+        lib.or_collide.restype = ctypes.c_double
+        lib.or_splitmix64.argtypes = [ctypes.c_uint64]
+        lib.or_splitmix64.restype = ctypes.c_uint64
+        lib.or_init.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_uint64, P]
+        lib.or_step.argtypes = [P, P, P, P, P, P]
+        lib.or_run.argtypes = [P, P, P, P, ctypes.c_int64]
+        lib.or_macros.argtypes = [P, P, P, P, P, P, P]
+        lib.or_mass.argtypes = [P, P, P, P, P]
+        lib.or_last_error.restype = ctypes.c_int
+        if hasattr(lib, "or_collide_jacobian"):
+            lib.or_collide_jacobian.argtypes = [P, P, P]
+            lib.or_adjoint_step.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, P, P]
+            lib.or_adjoint_step.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lattice():
+    """(c [19,3] int, w [19] float64, opp [19] int) as the oracle defines them."""
+    lib = _load()
+    c = np.zeros((NQ, 3), np.int32)
+    w = np.zeros(NQ, np.float64)
+    opp = np.zeros(NQ, np.int32)
+    lib.or_lattice(_p(c), _p(w), _p(opp))
+    return c, w, opp
+
+
+def equilibrium(rho: float, u) -> np.ndarray:
+    lib = _load()
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.zeros(NQ, np.float64)
+    lib.or_equilibrium(float(rho), _p(u), _p(out))
+    return out
+
+
+def tau_eff(tau0, c_smag, delta, q, rho) -> float:
+    return _load().or_tau_eff(tau0, c_smag, delta, q, rho)
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().or_splitmix64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+class Oracle:
+    """One configured oracle lattice (geometry, faces, collision parameters)."""
+
+    def __init__(self, nx, ny, nz, faces, tau0, c_smag=0.0, delta=1.0, rho0=1.0,
+                 force=(0.0, 0.0, 0.0), solid=None, inflow=None):
+        self.shape = (nz, ny, nx)
+        self.cfg = _Cfg()
+        self.cfg.nx, self.cfg.ny, self.cfg.nz = nx, ny, nz
+        for k in range(6):
+            self.cfg.face[k] = int(faces[k])
+        self.cfg.tau0, self.cfg.c_smag, self.cfg.delta, self.cfg.rho0 = tau0, c_smag, delta, rho0
+        for a in range(3):
+            self.cfg.force[a] = float(force[a])
+        self.solid = np.zeros(self.shape, np.uint8) if solid is None else \
+            np.ascontiguousarray(solid, np.uint8).reshape(self.shape)
+        self.inflow = np.zeros((6, nz, 3), np.float64)
+        if inflow is not None:
+            for face, prof in inflow.items():
+                self.inflow[face] = np.asarray(prof, np.float64).reshape(nz, 3)
+        self.lib = _load()
+
+    @property
+    def n(self):
+        nz, ny, nx = self.shape
+        return nx * ny * nz
+
+    def _check(self, rc):
+        if rc != 0:
+            raise RuntimeError(f"oracle error {rc}")
+
+    def init(self, u0=None, amp=0.0, seed=0) -> np.ndarray:
+        nz = self.shape[0]
+        u0 = np.zeros((nz, 3)) if u0 is None else np.asarray(u0, np.float64)
+        if u0.ndim == 1:
+            u0 = np.tile(u0, (nz, 1))
+        u0 = np.ascontiguousarray(u0, np.float64)
+        f = np.zeros((NQ,) + self.shape, np.float64)
+        self._check(self.lib.or_init(ctypes.byref(self.cfg), _p(self.solid), _p(self.inflow), _p(u0),
+                                     float(amp), int(seed), _p(f)))
+        return f
+
+    def step(self, f: np.ndarray) -> np.ndarray:
+        f = np.ascontiguousarray(f, np.float64)
+        out = np.empty_like(f)
+        work = np.empty_like(f)
+        self._check(self.lib.or_step(ctypes.byref(self.cfg), _p(self.solid), _p(self.inflow), _p(f),
+                                     _p(out), _p(work)))
+        return out
+
+    def run(self, f: np.ndarray, steps: int) -> np.ndarray:
+        f = np.array(f, np.float64, order="C", copy=True)
+        self._check(self.lib.or_run(ctypes.byref(self.cfg), _p(self.solid), _p(self.inflow), _p(f),
+                                    int(steps)))
+        return f
+
+    def macros(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, np.float64)
+        rho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        nut = np.zeros(self.shape)
+        self.lib.or_macros(ctypes.byref(self.cfg), _p(self.solid), _p(self.inflow), _p(f), _p(rho),
+                           _p(u), _p(nut))
+        return rho, u, nut
+
+    def mass(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, np.float64)
+        m = np.zeros(1)
+        e = np.zeros(1)
+        self.lib.or_mass(ctypes.byref(self.cfg), _p(self.solid), _p(f), _p(m), _p(e))
+        return float(m[0]), float(e[0])
+
+    def collide(self, fcell):
+        """Collide one cell: returns (f*, rho, u, tau_eff)."""
+        fcell = np.ascontiguousarray(fcell, np.float64)
+        out = np.zeros(NQ)
+        rho = np.zeros(1)
+        u = np.zeros(3)
+        tau = self.lib.or_collide(ctypes.byref(self.cfg), _p(fcell), _p(out), _p(rho), _p(u))
+        return out, float(rho[0]), u, tau
+
+    def moments(self, fcell):
+        fcell = np.ascontiguousarray(fcell, np.float64)
+        rho = np.zeros(1)
+        u = np.zeros(3)
+        self.lib.or_moments(ctypes.byref(self.cfg), _p(fcell), _p(rho), _p(u))
+        return float(rho[0]), u
+
+    def q_invariant(self, fcell, feq):
+        pi = np.zeros(9)
+        q = self.lib.or_q_invariant(_p(np.ascontiguousarray(fcell, np.float64)),
+                                    _p(np.ascontiguousarray(feq, np.float64)), _p(pi))
+        return q, pi.reshape(3, 3)
