@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D3Q19 LBM-LES step on one MI355X.
+
+Workload: the kilometre-scale urban analogue, 800 x 800 x 128 cells (81.9M),
+buildings at plan-area fraction 0.30 (median height 12 cells), power-law
+inflow (alpha 0.22, 0.08 at z = 100) at 30 degrees on the x- and y- faces,
+zero-gradient outflow on x+ and y+, bounce-back ground, free-slip top,
+tau0 = 0.505, C = 0.1, FP32 storage.  Inputs are seeded and synthetic and
+sit in HBM before the timed region.
+
+Prints ONE JSON line: MLUPS (fluid-cell updates per second) of the FP32
+forward step, the step kernel's achieved HBM bandwidth against the 8 TB/s
+peak from HIP events around every launch in the timed region, the shifted
+binary16 / bfloat16 storage rates, and the FP64 CPU oracle timed on a
+bounded crop of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + achieved HBM GB/s (fwd FP32 vs FP16-storage; adjoint), 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+NQ = 19
+STORE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+
+
+def algorithmic_bytes(lat, storage):
+    """Bytes one step-kernel launch must move: interior fluid cells read and
+    write 19 populations, inflow cells write 19, solid cells nothing (the
+    solid-mask bits, N/8 bytes, are negligible and not counted)."""
+    fluid, interior = lat.cell_counts()
+    b = STORE_BYTES[storage]
+    return interior * 2 * NQ * b + (fluid - interior) * NQ * b
+
+
+def time_forward(w, storage, steps, warmup):
+    import torch
+
+    from paper_2607_04516_amd import binding
+    lat = binding.from_workload(w, storage=storage)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    lat.profile(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    lat.step(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    kern_ms, launches = lat.profile_read()
+    lat.profile(False)
+    fluid, _ = lat.cell_counts()
+    mlups = fluid * steps / (ms * 1e-3) / 1e6
+    per_launch_ms = kern_ms / max(launches, 1)
+    bytes_launch = algorithmic_bytes(lat, storage)
+    gbs = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    # sanity: the run stayed finite
+    m, e = lat.mass()
+    lat.close()
+    return {"mlups": mlups, "ms_per_step": ms / steps, "kernel_ms": per_launch_ms, "launches": launches,
+            "bytes_per_launch": bytes_launch, "achieved_gbs": gbs, "fluid_cells": fluid,
+            "mass": m, "energy": e}
+
+
+def cpu_baseline(w, seconds=12.0, crop=(160, 160)):
+    """The FP64 oracle (single thread) on a crop of the workload: the first
+    crop[0] x crop[1] columns with the full height, same faces and profiles."""
+    import numpy as np
+
+    import oracle
+    from paper_2607_04516_amd import workloads
+
+    cx, cy = crop
+    solid = np.ascontiguousarray(w.solid[:, :cy, :cx])
+    faces = {"periodic": oracle.PERIODIC, "inflow": oracle.INFLOW_EQ, "outflow": oracle.OUTFLOW_ZG,
+             "freeslip": oracle.FREESLIP, "wall": oracle.WALL}
+    o = oracle.Oracle(cx, cy, w.nz, [faces[f] for f in w.faces], tau0=w.tau0, c_smag=w.c_smag,
+                      solid=solid, inflow=w.inflow)
+    f = o.init(u0=w.u0, amp=w.noise_amp, seed=w.noise_seed)
+    fluid = int(solid.size - np.count_nonzero(solid))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = o.step(f)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    return {"value": fluid * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, 1 thread, {cx}x{cy}x{w.nz} crop of {w.name} "
+                      f"({fluid} fluid cells), {steps} steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage runs")
+    ap.add_argument("--nx", type=int, default=800)
+    ap.add_argument("--ny", type=int, default=800)
+    ap.add_argument("--nz", type=int, default=128)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU slab decomposition is a design, not a measured path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2607_04516_amd import binding, workloads
+    binding.load()
+    torch.cuda.set_device(0)
+
+    print(f"[bench] building workload {args.nx}x{args.ny}x{args.nz}", file=sys.stderr, flush=True)
+    w = workloads.urban_km("f32", nx=args.nx, ny=args.ny, nz=args.nz)
+    res = time_forward(w, args.storage, args.steps, args.warmup)
+    print(f"[bench] {args.storage}: {res['mlups']:.0f} MLUPS, kernel {res['kernel_ms']:.3f} ms, "
+          f"{res['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+
+    extra = {}
+    if not args.no_extra:
+        for s in ("f16s", "bf16s"):
+            r = time_forward(w, s, args.steps, args.warmup)
+            extra[s] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
+                        "kernel_ms": round(r["kernel_ms"], 4), "achieved_gbs": round(r["achieved_gbs"], 1),
+                        "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        "vs_f32_mlups": round(r["mlups"] / res["mlups"], 3)}
+            print(f"[bench] {s}: {r['mlups']:.0f} MLUPS, {r['achieved_gbs']:.0f} GB/s", file=sys.stderr,
+                  flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a crop", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    line = {
+        "metric": METRIC,
+        "value": round(res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: urban buildings PAF 0.30, median 12, power-law inflow 30 deg "
+                               f"on x-/y-, outflow x+/y+, wall ground, free-slip top, tau0 0.505, C 0.1",
+                   "cells": w.cells, "fluid_cells": res["fluid_cells"], "storage": args.storage,
+                   "layout": "SoA [19][z][y][x_pitch64], in-place A-A"},
+        "roofline": {"bound": "hbm", "achieved": round(res["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "lbm::k_step (even/odd A-A launches)",
+                     "kernel_ms": round(res["kernel_ms"], 4),
+                     "bytes_per_launch": res["bytes_per_launch"]},
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        line["storage_forms"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

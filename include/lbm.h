@@ -23,7 +23,9 @@
  *    15/16 = +-(1,0,-1); 17/18 = +-(0,1,-1).  Weights 1/3, 1/18, 1/36.
  *  - Element type of device arrays: "real" is double for an LBM_F64 context
  *    and float otherwise; "store" is the storage type of the context
- *    (double, float, IEEE binary16, bfloat16).
+ *    (double, float, IEEE binary16, bfloat16).  LBM_F16S stores 256*h (a
+ *    power-of-two scale that keeps the shifts in binary16's normal range);
+ *    every other codec stores h itself.  Stores round to nearest even.
  *  - Host pointers are read during the call and copied; device pointers are
  *    borrowed for the duration of the enqueued work only.  The context owns
  *    every allocation it makes (populations, mask bits, ghost planes,
@@ -172,6 +174,16 @@ int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
  * Solid and inflow cells get lam = 0. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
                      const void *probe_src, void *g_inflow);
+
+/* Kernel timing for measurement: while enabled, a pair of HIP events on the
+ * context's stream brackets every launch of the fused collide-and-stream
+ * kernel (not the outflow passes).  Enabling resets the record. */
+int lbm_profile(lbm_ctx *ctx, int32_t enable);
+
+/* Synchronise, then return the summed duration in ms of the bracketed
+ * step-kernel launches recorded since lbm_profile(ctx, 1) or the previous
+ * read, and their number; resets the record. */
+int lbm_profile_read(lbm_ctx *ctx, double *total_ms, int64_t *launches);
 
 /* Current time step t of the context's state. */
 int64_t lbm_time(const lbm_ctx *ctx);

@@ -18,7 +18,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = [os.path.join(_HERE, "lbm_oracle.c"), os.path.join(_HERE, "lbm_oracle_adjoint.c")]
+_SRC = [os.path.join(_HERE, "lbm_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PERIODIC, INFLOW_EQ, OUTFLOW_ZG, FREESLIP, WALL = 0, 1, 2, 3, 4
@@ -71,10 +71,11 @@ def _load():
         lib.or_macros.argtypes = [P, P, P, P, P, P, P]
         lib.or_mass.argtypes = [P, P, P, P, P]
         lib.or_last_error.restype = ctypes.c_int
-        if hasattr(lib, "or_collide_jacobian"):
-            lib.or_collide_jacobian.argtypes = [P, P, P]
-            lib.or_adjoint_step.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, P, P]
-            lib.or_adjoint_step.restype = ctypes.c_int
+        lib.or_collide_jacobian.argtypes = [P, P, P]
+        lib.or_adjoint_step.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, P, P]
+        lib.or_adjoint_step.restype = ctypes.c_int
+        lib.or_step_cell.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        lib.or_step_cell.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -201,3 +202,35 @@ class Oracle:
         q = self.lib.or_q_invariant(_p(np.ascontiguousarray(fcell, np.float64)),
                                     _p(np.ascontiguousarray(feq, np.float64)), _p(pi))
         return q, pi.reshape(3, 3)
+
+    def collide_jacobian(self, fcell):
+        """J[i, j] = d f*_i / d f_j of the collision of one cell."""
+        J = np.zeros((NQ, NQ))
+        self.lib.or_collide_jacobian(ctypes.byref(self.cfg), _p(np.ascontiguousarray(fcell, np.float64)), _p(J))
+        return J
+
+    def adjoint_step(self, f_t, lam_next, probes=None, probe_src=None):
+        """lam(t) = (d f(t+1)/d f(t))^T lam_next + probe sources at time t, and
+        the gradient of the step with respect to the inflow profiles [6, nz, 3]."""
+        f_t = np.ascontiguousarray(f_t, np.float64)
+        lam_next = np.ascontiguousarray(lam_next, np.float64)
+        lam = np.zeros_like(f_t)
+        work = np.zeros_like(f_t)
+        g = np.zeros((6, self.shape[0], 3))
+        if probes is None:
+            pr, np_, src = None, 0, None
+        else:
+            pr = np.ascontiguousarray(probes, np.int32).reshape(-1, 3)
+            np_ = pr.shape[0]
+            src = None if probe_src is None else np.ascontiguousarray(probe_src, np.float64).reshape(-1, 3)
+        self._check(self.lib.or_adjoint_step(ctypes.byref(self.cfg), _p(self.solid), _p(self.inflow), _p(f_t),
+                                             _p(lam_next), _p(lam), None if pr is None else _p(pr), np_,
+                                             None if src is None else _p(src), _p(g), _p(work)))
+        return lam, g
+
+    def step_cell(self, window, x, y, z):
+        """f(x, t+1) of one cell from the 5x5x5 window of f(t) around it."""
+        out = np.zeros(NQ)
+        self._check(self.lib.or_step_cell(ctypes.byref(self.cfg), _p(self.solid), _p(self.inflow),
+                                          _p(np.ascontiguousarray(window, np.float64)), x, y, z, _p(out)))
+        return out

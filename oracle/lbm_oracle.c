@@ -211,11 +211,13 @@ static void inflow_velocity(const or_cfg *g, const double *inflow, int face, con
 }
 
 /* ------------------------------------------------------------------ */
-/* Streaming resolution: value of f_i at the non-solid, non-inflow cell p
- * after streaming, from the post-collision field fs.                    */
-static double pull_plain(const or_cfg *g, const uint8_t *solid, const double *fs, int64_t n, int i, const int *p)
+/* Streaming resolution: the post-collision slot (j, s) whose value f*_j(s)
+ * becomes f_i at the non-solid, non-inflow cell p after streaming, returned
+ * as the flat index j*N + n(s), or -1 if the rules are violated.        */
+static int64_t source_plain(const or_cfg *g, const uint8_t *solid, int i, const int *p)
 {
     int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    int64_t n = IDX(g, p[0], p[1], p[2]);
     int s[3], j = i;
     for (int a = 0; a < 3; a++) s[a] = p[a] - CV[i][a];
     for (int a = 0; a < 3; a++) {
@@ -223,7 +225,7 @@ static double pull_plain(const or_cfg *g, const uint8_t *solid, const double *fs
         int kind = g->face[s[a] < 0 ? 2 * a : 2 * a + 1];
         if (kind == OR_WALL) {
             /* halfway bounce-back at the face plane (App. D, bounce-back) */
-            return fs[opposite(i) * N + n];
+            return opposite(i) * N + n;
         } else if (kind == OR_PERIODIC) {
             s[a] = (s[a] + dim(g, a)) % dim(g, a);
         } else if (kind == OR_FREESLIP) {
@@ -233,14 +235,14 @@ static double pull_plain(const or_cfg *g, const uint8_t *solid, const double *fs
         } else {
             /* an inflow or outflow face is never crossed by a pull from here */
             g_err = 2;
-            return NAN;
+            return -1;
         }
     }
-    if (is_solid(g, solid, s)) return fs[opposite(i) * N + n]; /* halfway bounce-back */
-    return fs[j * N + IDX(g, s[0], s[1], s[2])];
+    if (is_solid(g, solid, s)) return opposite(i) * N + n; /* halfway bounce-back */
+    return j * N + IDX(g, s[0], s[1], s[2]);
 }
 
-static double pull_resolve(const or_cfg *g, const uint8_t *solid, const double *fs, int i, const int *p)
+static int64_t source_of(const or_cfg *g, const uint8_t *solid, int i, const int *p)
 {
     int64_t N = (int64_t)g->nx * g->ny * g->nz;
     int64_t n = IDX(g, p[0], p[1], p[2]);
@@ -258,10 +260,16 @@ static double pull_resolve(const or_cfg *g, const uint8_t *solid, const double *
         }
     }
     if (moved) {
-        if (is_solid(g, solid, q)) return fs[opposite(i) * N + n];
-        return pull_plain(g, solid, fs, IDX(g, q[0], q[1], q[2]), i, q);
+        if (is_solid(g, solid, q)) return opposite(i) * N + n;
+        return source_plain(g, solid, i, q);
     }
-    return pull_plain(g, solid, fs, n, i, p);
+    return source_plain(g, solid, i, p);
+}
+
+static double pull_resolve(const or_cfg *g, const uint8_t *solid, const double *fs, int i, const int *p)
+{
+    int64_t k = source_of(g, solid, i, p);
+    return k < 0 ? NAN : fs[k];
 }
 
 /* ------------------------------------------------------------------ */
@@ -443,4 +451,209 @@ void or_mass(const or_cfg *g, const uint8_t *solid, const double *f, double *mas
             }
     *mass = m;
     *energy = e;
+}
+
+/* ------------------------------------------------------------------ */
+/* Discrete adjoint (test infrastructure for the adjoint kernel).
+ *
+ * Forward step, written as a map of the state: f(t+1) = S(C(f(t)), u_in),
+ * with C the local collision of every fluid cell and S the streaming with
+ * its boundary rules, inflow cells supplying feq(rho0, u_in).  Its
+ * transpose applied to lam_next = dL/df(t+1) is computed literally:
+ *   1. scatter-add: every pull (x, i) <- (j, s) adds lam_next[i][x] into
+ *      lam_star[j][s] (the outflow copy adds twice into one source);
+ *   2. lam[.][s] = J(f_t(s))^T lam_star[.][s] with J the explicit 19x19
+ *      Jacobian of the collision, for every fluid cell;
+ *   3. inflow cells turn lam_star into the gradient of their profile:
+ *      g[face][z] += sum_j lam_star[j] d feq_j(rho0, u)/du;
+ *   4. probe cells add dL/du(x_p, t) . du/df_j = src . (c_j - u)/rho.
+ * Solid and inflow cells get lam = 0.                                    */
+
+/* J[i*19 + j] = d f*_i / d f_j of or_collide, term by term. */
+void or_collide_jacobian(const or_cfg *g, const double *f, double *J)
+{
+    const double cs2 = 1.0 / 3.0;
+    double rho, u[3], feq[NQ], pi[9];
+    or_moments(g, f, &rho, u);
+    or_equilibrium(rho, u, feq);
+    double q = or_q_invariant(f, feq, pi);
+    double tau = or_tau_eff(g->tau0, g->c_smag, g->delta, q, rho);
+    double omega = 1.0 / tau;
+    double cd = g->c_smag * g->delta;
+    double K = 2.0 * cd * cd / (cs2 * cs2);
+    double D = g->tau0 * g->tau0 + K * q / rho;
+
+    /* d u_a / d f_j = (c_ja - u_a) / rho   (rho u = sum c f + F/2) */
+    double du[3][NQ];
+    for (int a = 0; a < 3; a++)
+        for (int j = 0; j < NQ; j++) du[a][j] = (CV[j][a] - u[a]) / rho;
+
+    /* d feq_i / d f_j = feq_i / rho + sum_a (d feq_i / d u_a) (d u_a / d f_j) */
+    double dfeq[NQ][NQ];
+    for (int i = 0; i < NQ; i++) {
+        double e = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+        double dfdu[3];
+        for (int a = 0; a < 3; a++)
+            dfdu[a] = weight(i) * rho * (CV[i][a] / cs2 + e * CV[i][a] / (cs2 * cs2) - u[a] / cs2);
+        for (int j = 0; j < NQ; j++) {
+            double v = feq[i] / rho;
+            for (int a = 0; a < 3; a++) v += dfdu[a] * du[a][j];
+            dfeq[i][j] = v;
+        }
+    }
+
+    /* d Pi_ab / d f_j = c_ja c_jb - sum_i c_ia c_ib d feq_i / d f_j;
+     * d Q / d f_j = 2 Pi:dPi / Q (taken as 0 at Q = 0) */
+    double dq[NQ];
+    for (int j = 0; j < NQ; j++) {
+        double s = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double dp = CV[j][a] * CV[j][b];
+                for (int i = 0; i < NQ; i++) dp -= CV[i][a] * CV[i][b] * dfeq[i][j];
+                s += pi[3 * a + b] * dp;
+            }
+        dq[j] = q > 0.0 ? 2.0 * s / q : 0.0;
+    }
+
+    /* tau = (tau0 + sqrt(D))/2, D = tau0^2 + K Q / rho, d rho / d f_j = 1 */
+    double domega[NQ];
+    for (int j = 0; j < NQ; j++) {
+        double dD = K * (dq[j] / rho - q / (rho * rho));
+        double dtau = 0.25 * dD / sqrt(D);
+        domega[j] = -dtau / (tau * tau);
+    }
+
+    for (int i = 0; i < NQ; i++) {
+        double e = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+        double B = 0.0;
+        for (int a = 0; a < 3; a++) B += (3.0 * (CV[i][a] - u[a]) + 9.0 * e * CV[i][a]) * g->force[a];
+        for (int j = 0; j < NQ; j++) {
+            double dB = 0.0;
+            double cdu = CV[i][0] * du[0][j] + CV[i][1] * du[1][j] + CV[i][2] * du[2][j];
+            for (int a = 0; a < 3; a++) dB += g->force[a] * (-3.0 * du[a][j] + 9.0 * CV[i][a] * cdu);
+            double dS = -0.5 * domega[j] * weight(i) * B + (1.0 - 0.5 * omega) * weight(i) * dB;
+            double kd = (i == j) ? 1.0 : 0.0;
+            J[i * NQ + j] = kd - domega[j] * (f[i] - feq[i]) - omega * (kd - dfeq[i][j]) + dS;
+        }
+    }
+}
+
+int or_adjoint_step(const or_cfg *g, const uint8_t *solid, const double *inflow, const double *f_t,
+                    const double *lam_next, double *lam, const int32_t *probes, int32_t np,
+                    const double *probe_src, double *g_inflow, double *work)
+{
+    g_err = check_cfg(g);
+    if (g_err) return g_err;
+    int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    double *lam_star = work;
+    for (int64_t k = 0; k < NQ * N; k++) lam_star[k] = 0.0;
+
+    /* 1. transpose of the streaming: scatter-add over every pull */
+    for (int z = 0; z < g->nz; z++)
+        for (int y = 0; y < g->ny; y++)
+            for (int x = 0; x < g->nx; x++) {
+                int p[3] = {x, y, z};
+                int64_t n = IDX(g, x, y, z);
+                if (is_solid(g, solid, p) || inflow_face(g, p) >= 0) continue;
+                for (int i = 0; i < NQ; i++) {
+                    int64_t k = source_of(g, solid, i, p);
+                    if (k < 0) return g_err;
+                    lam_star[k] += lam_next[i * N + n];
+                }
+            }
+
+    /* 2./3. transpose of the collision; inflow parameter sources */
+    for (int z = 0; z < g->nz; z++)
+        for (int y = 0; y < g->ny; y++)
+            for (int x = 0; x < g->nx; x++) {
+                int p[3] = {x, y, z};
+                int64_t n = IDX(g, x, y, z);
+                for (int j = 0; j < NQ; j++) lam[j * N + n] = 0.0;
+                if (is_solid(g, solid, p)) continue;
+                int face = inflow_face(g, p);
+                if (face >= 0) {
+                    double u[3];
+                    inflow_velocity(g, inflow, face, p, u);
+                    double *gz = g_inflow + ((int64_t)face * g->nz + z) * 3;
+                    for (int j = 0; j < NQ; j++) {
+                        double e = CV[j][0] * u[0] + CV[j][1] * u[1] + CV[j][2] * u[2];
+                        for (int a = 0; a < 3; a++)
+                            gz[a] += lam_star[j * N + n] * weight(j) * g->rho0 *
+                                     (3.0 * CV[j][a] + 9.0 * e * CV[j][a] - 3.0 * u[a]);
+                    }
+                    continue;
+                }
+                double fc[NQ], J[NQ * NQ];
+                for (int i = 0; i < NQ; i++) fc[i] = f_t[i * N + n];
+                or_collide_jacobian(g, fc, J);
+                for (int j = 0; j < NQ; j++) {
+                    double s = 0.0;
+                    for (int i = 0; i < NQ; i++) s += J[i * NQ + j] * lam_star[i * N + n];
+                    lam[j * N + n] = s;
+                }
+            }
+
+    /* 4. probe sources dL/du(x_p, t) . du/df */
+    for (int k = 0; k < np && probe_src; k++) {
+        int p[3] = {probes[3 * k], probes[3 * k + 1], probes[3 * k + 2]};
+        if (is_solid(g, solid, p) || inflow_face(g, p) >= 0) continue;
+        int64_t n = IDX(g, p[0], p[1], p[2]);
+        double fc[NQ], rho, u[3];
+        for (int i = 0; i < NQ; i++) fc[i] = f_t[i * N + n];
+        or_moments(g, fc, &rho, u);
+        for (int j = 0; j < NQ; j++)
+            for (int a = 0; a < 3; a++) lam[j * N + n] += probe_src[3 * k + a] * (CV[j][a] - u[a]) / rho;
+    }
+    return 0;
+}
+
+/* f(x, t+1) at one non-solid cell x from a 5x5x5 window of f(t) centred on
+ * x (window index [i][dz+2][dy+2][dx+2], periodic coordinates wrapped), by
+ * colliding on demand the cells the pulls reach.  Used to check single
+ * cells of grids too large for a full oracle step. */
+int or_step_cell(const or_cfg *g, const uint8_t *solid, const double *inflow, const double *win,
+                 int x, int y, int z, double *out)
+{
+    g_err = check_cfg(g);
+    if (g_err) return g_err;
+    int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    int p[3] = {x, y, z};
+    if (is_solid(g, solid, p)) return 4;
+    int face = inflow_face(g, p);
+    if (face >= 0) {
+        double u[3];
+        inflow_velocity(g, inflow, face, p, u);
+        or_equilibrium(g->rho0, u, out);
+        return 0;
+    }
+    for (int i = 0; i < NQ; i++) {
+        int64_t k = source_of(g, solid, i, p);
+        if (k < 0) return g_err;
+        int j = (int)(k / N);
+        int64_t n = k % N;
+        int s[3] = {(int)(n % g->nx), (int)((n / g->nx) % g->ny), (int)(n / ((int64_t)g->nx * g->ny))};
+        int sf = inflow_face(g, s);
+        double fo[NQ];
+        if (sf >= 0) {
+            double u[3];
+            inflow_velocity(g, inflow, sf, s, u);
+            or_equilibrium(g->rho0, u, fo);
+        } else {
+            int d[3];
+            for (int a = 0; a < 3; a++) {
+                int n_a = dim(g, a);
+                d[a] = s[a] - p[a];
+                if (d[a] > n_a / 2) d[a] -= n_a;   /* periodic wrap back to the nearest image */
+                if (d[a] < -n_a / 2) d[a] += n_a;
+                if (d[a] < -2 || d[a] > 2) return 5;
+            }
+            double fc[NQ];
+            for (int m = 0; m < NQ; m++)
+                fc[m] = win[(((int64_t)m * 5 + (d[2] + 2)) * 5 + (d[1] + 2)) * 5 + (d[0] + 2)];
+            or_collide(g, fc, fo, NULL, NULL);
+        }
+        out[i] = fo[j];
+    }
+    return 0;
 }

@@ -1,0 +1,410 @@
+// Device-side building blocks of the D3Q19 LBM-LES library for gfx950:
+// the velocity set, storage codecs, the boundary resolution of one
+// population, and the local BGK + Smagorinsky collision
+// (arXiv 2607.04516, App. D, eqs. D.1-D.11).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int NQ = 19;
+
+struct V3 {
+    int x, y, z;
+};
+
+// D3Q19 velocities: rest, +-x, +-y, +-z, then +-(1,1,0), +-(1,0,1), +-(0,1,1),
+// +-(1,-1,0), +-(1,0,-1), +-(0,1,-1).  Directions 2k-1 and 2k are opposite.
+__host__ __device__ constexpr V3 dirv(int i)
+{
+    const V3 t[NQ] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                      {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, 0, 1},
+                      {-1, 0, -1}, {0, 1, 1}, {0, -1, -1}, {1, -1, 0}, {-1, 1, 0},
+                      {1, 0, -1}, {-1, 0, 1}, {0, 1, -1}, {0, -1, 1}};
+    return t[i];
+}
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+__host__ __device__ constexpr int comp(V3 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
+
+__host__ __device__ constexpr int dir_index(int x, int y, int z)
+{
+    for (int i = 0; i < NQ; i++) {
+        V3 v = dirv(i);
+        if (v.x == x && v.y == y && v.z == z) return i;
+    }
+    return -1;
+}
+
+// Direction with the components selected by the bit mask m (bit a = axis a) negated.
+__host__ __device__ constexpr int mirrored(int i, int m)
+{
+    V3 v = dirv(i);
+    return dir_index((m & 1) ? -v.x : v.x, (m & 2) ? -v.y : v.y, (m & 4) ? -v.z : v.z);
+}
+
+// Position k (0..4) of direction i among the five directions whose component
+// a equals s, in increasing direction order (-1 when comp(i, a) != s).
+__host__ __device__ constexpr int entering_rank(int i, int a, int s)
+{
+    int k = 0;
+    for (int j = 0; j < NQ; j++) {
+        if (comp(dirv(j), a) != s) continue;
+        if (j == i) return k;
+        k++;
+    }
+    return -1;
+}
+
+template <typename T>
+__host__ __device__ constexpr T weight(int i)
+{
+    return i == 0 ? T(1) / T(3) : (i <= 6 ? T(1) / T(18) : T(1) / T(36));
+}
+
+// Face kinds (same values as enum lbm_face_kind in lbm.h).
+enum { F_PERIODIC = 0, F_INFLOW = 1, F_OUTFLOW = 2, F_FREESLIP = 3, F_WALL = 4 };
+
+// --------------------------------------------------------------------------
+// Storage codecs: what one population occupies in HBM.  The stored quantity
+// is always the shift h = f - w*rho0 (times a power-of-two scale for binary16
+// so that the values sit in its normal range).
+// --------------------------------------------------------------------------
+template <int K>
+struct Codec;
+
+template <>
+struct Codec<0> {  // FP64
+    using store = double;
+    using real = double;
+    __device__ static real dec(store v) { return v; }
+    __device__ static store enc(real v) { return v; }
+};
+
+template <>
+struct Codec<1> {  // FP32
+    using store = float;
+    using real = float;
+    __device__ static real dec(store v) { return v; }
+    __device__ static store enc(real v) { return v; }
+};
+
+template <>
+struct Codec<2> {  // IEEE binary16, round to nearest even, scaled by 2^8
+    using store = _Float16;
+    using real = float;
+    static constexpr float scale = 256.0f;
+    __device__ static real dec(store v) { return float(v) * (1.0f / scale); }
+    __device__ static store enc(real v) { return store(v * scale); }
+};
+
+template <>
+struct Codec<3> {  // bfloat16, round to nearest even
+    using store = uint16_t;
+    using real = float;
+    __device__ static real dec(store v) { return __uint_as_float(uint32_t(v) << 16); }
+    __device__ static store enc(real v)
+    {
+        uint32_t u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return store(u >> 16);
+    }
+};
+
+// --------------------------------------------------------------------------
+// Geometry and parameters (passed by value to every kernel).
+// --------------------------------------------------------------------------
+struct Geo {
+    int nx, ny, nz;
+    int pitch;           // x pitch of the in-place population array (multiple of 64)
+    int wpr;             // 64-bit mask words per row
+    int ncx;             // 64-cell chunks per row = pitch / 64
+    int face[6];         // face kinds, order x-, x+, y-, y+, z-, z+
+    long long S;         // slice stride of the in-place array = pitch*ny*nz
+    long long N;         // nx*ny*nz
+    long long ghost_off[6];  // element offset of each outflow face's ghost block
+};
+
+template <typename R>
+struct Phys {
+    R tau0;
+    R ksmag;       // 18 (C Delta)^2 = 2 (C Delta)^2 / cs^4
+    R rho0;
+    R F[3];        // body force
+    int has_force;
+};
+
+// Layout of one population array: index = dir*S + x + pitch*(y + ny*z).
+struct Lay {
+    long long S;
+    int pitch;
+};
+
+__device__ inline long long cell_index(const Lay& L, int ny, int x, int y, int z)
+{
+    return (long long)x + (long long)L.pitch * ((long long)y + (long long)ny * z);
+}
+
+__device__ inline bool solid_at(const uint64_t* __restrict__ mask, const Geo& g, int x, int y, int z)
+{
+    uint64_t w = mask[(long long)(y + (long long)g.ny * z) * g.wpr + (x >> 6)];
+    return (w >> (x & 63)) & 1ull;
+}
+
+__device__ inline int dimn(const Geo& g, int a) { return a == 0 ? g.nx : (a == 1 ? g.ny : g.nz); }
+
+// Lowest-numbered inflow face whose layer holds (x,y,z), or -1.
+__device__ inline int inflow_face_of(const Geo& g, int x, int y, int z)
+{
+    if (g.face[0] == F_INFLOW && x == 0) return 0;
+    if (g.face[1] == F_INFLOW && x == g.nx - 1) return 1;
+    if (g.face[2] == F_INFLOW && y == 0) return 2;
+    if (g.face[3] == F_INFLOW && y == g.ny - 1) return 3;
+    if (g.face[4] == F_INFLOW && z == 0) return 4;
+    if (g.face[5] == F_INFLOW && z == g.nz - 1) return 5;
+    return -1;
+}
+
+// --------------------------------------------------------------------------
+// Boundary resolution of direction I at a non-solid cell p = (x,y,z).
+//
+// The streaming (eq. D.3) pulls f_I(p, t+1) = f*_j(s, t) with s = p - c_I,
+// j = I, and the face rules for each axis the pull leaves the grid through:
+//   WALL      halfway bounce-back: the value is f*_opp(I)(p)
+//   PERIODIC  s wraps
+//   FREESLIP  specular reflection: j mirrors that component, s_a = p_a
+//   INFLOW / OUTFLOW never crossed by a pull from a fluid cell
+// and halfway bounce-back when s is solid (App. D, last paragraph).
+//
+// The same slot serves the pull of direction I and the push of direction
+// opp(I) (the streaming rules are time reversible), which is what makes the
+// in-place A-A update race free.  Res.kind:
+//   0  slot (x,y,z,dir): the pull reads the post-collision value stored at
+//      (s, opp(j)) in the swapped layout; bounce-back gives (p, I)
+//   2  no slot: the pull leaves through an inflow or outflow face
+// --------------------------------------------------------------------------
+struct Res {
+    int kind;
+    int x, y, z;
+    int dir;
+};
+
+template <int I>
+__device__ inline Res resolve_plain(const Geo& g, const uint64_t* __restrict__ mask, int x, int y, int z)
+{
+    constexpr V3 c = dirv(I);
+    int s[3] = {x - c.x, y - c.y, z - c.z};
+    const int p[3] = {x, y, z};
+    int m = 0;  // mirrored axes
+    Res r;
+    r.kind = 0;
+    r.x = x; r.y = y; r.z = z; r.dir = I;  // valid in-bounds slot even when kind == 2
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int ca = comp(c, a);
+        if (ca == 0) continue;
+        const int n = dimn(g, a);
+        const bool lo = (s[a] < 0), hi = (s[a] >= n);
+        if (!(lo || hi)) continue;
+        const int kind = g.face[lo ? 2 * a : 2 * a + 1];
+        if (kind == F_WALL) {
+            r.x = x; r.y = y; r.z = z; r.dir = I;
+            return r;
+        } else if (kind == F_PERIODIC) {
+            s[a] = lo ? s[a] + n : s[a] - n;
+        } else if (kind == F_FREESLIP) {
+            m |= (1 << a);
+            s[a] = p[a];
+        } else {
+            r.kind = 2;
+            return r;
+        }
+    }
+    if (solid_at(mask, g, s[0], s[1], s[2])) {
+        r.x = x; r.y = y; r.z = z; r.dir = I;
+        return r;
+    }
+    // j = I with the mirrored components flipped; the value sits in slot opp(j)
+    constexpr int o0 = opp(mirrored(I, 0)), o1 = opp(mirrored(I, 1)), o2 = opp(mirrored(I, 2)),
+                  o3 = opp(mirrored(I, 3)), o4 = opp(mirrored(I, 4)), o5 = opp(mirrored(I, 5)),
+                  o6 = opp(mirrored(I, 6)), o7 = opp(mirrored(I, 7));
+    int d;
+    switch (m) {
+        case 0: d = o0; break;
+        case 1: d = o1; break;
+        case 2: d = o2; break;
+        case 3: d = o3; break;
+        case 4: d = o4; break;
+        case 5: d = o5; break;
+        case 6: d = o6; break;
+        default: d = o7; break;
+    }
+    r.x = s[0]; r.y = s[1]; r.z = s[2]; r.dir = d;
+    return r;
+}
+
+// Zero-gradient outflow: when direction I enters through an outflow face at
+// p, f_I(p) copies what the cell q (p moved one layer inward along every such
+// face) receives.  Returns true in that case with q and the lowest-numbered
+// such face (the owner of the ghost entry).
+template <int I>
+__device__ inline bool outflow_entering(const Geo& g, int x, int y, int z, int& qx, int& qy, int& qz, int& owner)
+{
+    constexpr V3 c = dirv(I);
+    bool moved = false;
+    owner = 6;
+    qx = x; qy = y; qz = z;
+    if (c.x == 1 && g.face[0] == F_OUTFLOW && x == 0) { qx = 1; moved = true; owner = min(owner, 0); }
+    if (c.x == -1 && g.face[1] == F_OUTFLOW && x == g.nx - 1) { qx = g.nx - 2; moved = true; owner = min(owner, 1); }
+    if (c.y == 1 && g.face[2] == F_OUTFLOW && y == 0) { qy = 1; moved = true; owner = min(owner, 2); }
+    if (c.y == -1 && g.face[3] == F_OUTFLOW && y == g.ny - 1) { qy = g.ny - 2; moved = true; owner = min(owner, 3); }
+    if (c.z == 1 && g.face[4] == F_OUTFLOW && z == 0) { qz = 1; moved = true; owner = min(owner, 4); }
+    if (c.z == -1 && g.face[5] == F_OUTFLOW && z == g.nz - 1) { qz = g.nz - 2; moved = true; owner = min(owner, 5); }
+    return moved;
+}
+
+// Index of the ghost entry for (face, direction I, cell p).
+template <int I>
+__device__ inline long long ghost_index(const Geo& g, int face, int x, int y, int z)
+{
+    const int a = face >> 1;
+    const int s = (face & 1) ? -1 : 1;
+    int k;
+    long long cell;
+    if (a == 0) { k = entering_rank(I, 0, s); cell = y + (long long)g.ny * z; }
+    else if (a == 1) { k = entering_rank(I, 1, s); cell = x + (long long)g.nx * z; }
+    else { k = entering_rank(I, 2, s); cell = x + (long long)g.nx * y; }
+    long long fc = (a == 0) ? (long long)g.ny * g.nz : (a == 1 ? (long long)g.nx * g.nz : (long long)g.nx * g.ny);
+    return g.ghost_off[face] + (long long)k * fc + cell;
+}
+
+// Full resolution of the pull of direction I at a fluid (non-solid,
+// non-inflow) cell, outflow copy included; kind 0 slot in the swapped layout.
+template <int I>
+__device__ inline Res resolve_full(const Geo& g, const uint64_t* __restrict__ mask, int x, int y, int z)
+{
+    int qx, qy, qz, owner;
+    if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
+        if (solid_at(mask, g, qx, qy, qz)) {
+            Res r;
+            r.kind = 0; r.x = x; r.y = y; r.z = z; r.dir = I;
+            return r;
+        }
+        return resolve_plain<I>(g, mask, qx, qy, qz);
+    }
+    return resolve_plain<I>(g, mask, x, y, z);
+}
+
+// --------------------------------------------------------------------------
+// Equilibrium of the shifted populations (eq. D.4 minus w_i rho0):
+//   heq_i = w_i (rho - rho0) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)
+// --------------------------------------------------------------------------
+template <typename R>
+__device__ inline void equilibrium_shifted(R rho, R drho, R ux, R uy, R uz, R* heq)
+{
+    const R usq15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    heq[0] = weight<R>(0) * (drho - rho * usq15);
+#pragma unroll
+    for (int k = 1; k < NQ; k += 2) {
+        const V3 c = dirv(k);
+        const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
+        const R w = weight<R>(k);
+        const R even = w * (drho + rho * (R(4.5) * e * e - usq15));
+        const R odd = w * rho * (R(3) * e);
+        heq[k] = even + odd;
+        heq[k + 1] = even - odd;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Local collision of one cell on shifted populations h (in place):
+//   rho = rho0 + sum h, rho u = sum c h (+ F/2)             (eq. D.1)
+//   Pi = sum c c (h - heq), Q = sqrt(2 Pi:Pi)                (eqs. D.8, D.10)
+//   tau_eff = (tau0 + sqrt(tau0^2 + 18 (C Delta)^2 Q / rho)) / 2   (eq. D.11)
+//   h*_i = h_i - (h_i - heq_i)/tau_eff (+ Guo source)        (eq. D.2)
+// Returns rho - rho0, u and tau_eff through the out parameters.
+// --------------------------------------------------------------------------
+// Moments of shifted populations (eq. D.1): rho - rho0 = sum h, and
+// u = (sum c h + F/2) / rho.  One fixed summation order, shared by the
+// collision and every diagnostic so that they agree to the last bit.
+template <typename R>
+__device__ inline void moments(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz, R& inv_rho)
+{
+    R d = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
+    d += ((h[8] + h[9]) + (h[10] + h[11])) + ((h[12] + h[13]) + (h[14] + h[15]));
+    d += (h[16] + h[17]) + h[18];
+    R jx = ((h[1] - h[2]) + (h[7] - h[8])) + ((h[9] - h[10]) + (h[13] - h[14])) + (h[15] - h[16]);
+    R jy = ((h[3] - h[4]) + (h[7] - h[8])) + ((h[11] - h[12]) + (h[14] - h[13])) + (h[17] - h[18]);
+    R jz = ((h[5] - h[6]) + (h[9] - h[10])) + ((h[11] - h[12]) + (h[16] - h[15])) + (h[18] - h[17]);
+    if (P.has_force) {
+        jx += R(0.5) * P.F[0];
+        jy += R(0.5) * P.F[1];
+        jz += R(0.5) * P.F[2];
+    }
+    inv_rho = R(1) / (P.rho0 + d);
+    drho = d;
+    ux = jx * inv_rho;
+    uy = jy * inv_rho;
+    uz = jz * inv_rho;
+}
+
+// --------------------------------------------------------------------------
+// Local collision of one cell on shifted populations h (in place):
+//   rho = rho0 + sum h, rho u = sum c h (+ F/2)             (eq. D.1)
+//   Pi = sum c c (h - heq), Q = sqrt(2 Pi:Pi)                (eqs. D.8, D.10)
+//   tau_eff = (tau0 + sqrt(tau0^2 + 18 (C Delta)^2 Q / rho)) / 2   (eq. D.11)
+//   h*_i = h_i - (h_i - heq_i)/tau_eff (+ Guo source)        (eq. D.2)
+// Returns rho - rho0, u and tau_eff through the out parameters.
+// --------------------------------------------------------------------------
+template <typename R>
+__device__ inline void collide(R* h, const Phys<R>& P, R& drho_out, R& ux, R& uy, R& uz, R& tau_out)
+{
+    R drho, inv_rho;
+    moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+    const R rho = P.rho0 + drho;
+    R neq[NQ];
+    equilibrium_shifted<R>(rho, drho, ux, uy, uz, neq);
+#pragma unroll
+    for (int i = 0; i < NQ; i++) neq[i] = h[i] - neq[i];
+    const R pxx = ((neq[1] + neq[2]) + (neq[7] + neq[8])) + ((neq[9] + neq[10]) + (neq[13] + neq[14])) + (neq[15] + neq[16]);
+    const R pyy = ((neq[3] + neq[4]) + (neq[7] + neq[8])) + ((neq[11] + neq[12]) + (neq[13] + neq[14])) + (neq[17] + neq[18]);
+    const R pzz = ((neq[5] + neq[6]) + (neq[9] + neq[10])) + ((neq[11] + neq[12]) + (neq[15] + neq[16])) + (neq[17] + neq[18]);
+    const R pxy = (neq[7] + neq[8]) - (neq[13] + neq[14]);
+    const R pxz = (neq[9] + neq[10]) - (neq[15] + neq[16]);
+    const R pyz = (neq[11] + neq[12]) - (neq[17] + neq[18]);
+    const R pp = (pxx * pxx + pyy * pyy + pzz * pzz) + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+    const R q = sqrt(R(2) * pp);
+    const R tau = R(0.5) * (P.tau0 + sqrt(P.tau0 * P.tau0 + P.ksmag * q * inv_rho));
+    const R omega = R(1) / tau;
+#pragma unroll
+    for (int i = 0; i < NQ; i++) h[i] = h[i] - omega * neq[i];
+    if (P.has_force) {
+        // Guo source (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F
+        const R uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+        const R pre = R(1) - R(0.5) * omega;
+#pragma unroll
+        for (int i = 0; i < NQ; i++) {
+            const V3 c = dirv(i);
+            const R cu = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
+            const R cF = R(c.x) * P.F[0] + R(c.y) * P.F[1] + R(c.z) * P.F[2];
+            h[i] += pre * weight<R>(i) * (R(3) * (cF - uF) + R(9) * cu * cF);
+        }
+    }
+    drho_out = drho;
+    tau_out = tau;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): golden-gamma increment, then the
+// published finaliser.
+__host__ __device__ inline uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace lbm

@@ -1,0 +1,774 @@
+// HIP kernels of the D3Q19 LBM-LES update for gfx950 (arXiv 2607.04516,
+// App. D): the fused in-place A-A collide-and-stream step, the out-of-place
+// push step used to recompute trajectories, zero-gradient outflow passes,
+// initialisation, state export/import, macroscopic fields, probes and
+// reductions.
+//
+// In-place A-A streaming on the SoA array f[dir][z][y][x]:
+//   even step  each cell reads its own 19 slots (natural layout: slot i of
+//              cell x holds f_i(x)), collides, and writes f*_i back into
+//              its own slot opp(i) (swapped layout);
+//   odd step   each cell gathers f_i(x) = f*_i(x - c_i) from slot opp(i) of
+//              the neighbour, collides, and scatters f*_i(x) into slot i of
+//              cell x + c_i (natural layout again).
+// Every slot is read and written by exactly one thread per step, so the
+// update needs one array and no synchronisation.  The boundary rules enter
+// only through the slot each direction resolves to (lbm_device.h).
+#include "lbm_device.h"
+#include "lbm_launch.h"
+
+#include <type_traits>
+
+namespace lbm {
+
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn)
+{
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(fn);
+    }
+}
+
+constexpr int MODE_EVEN = 0, MODE_ODD = 1, MODE_PUSH = 2;
+
+template <typename R>
+__device__ inline void load_profile(const double* __restrict__ prof, int nz, int face, int z, R& ux, R& uy, R& uz)
+{
+    const double* p = prof + ((long long)face * nz + z) * 3;
+    ux = R(p[0]);
+    uy = R(p[1]);
+    uz = R(p[2]);
+}
+
+// Wave -> (chunk, y, z) with a block order that keeps consecutive chunks of a
+// row on one XCD (blocks are dealt to the 8 XCDs round robin).
+__device__ inline long long xcd_block(long long nblocks_padded)
+{
+    const long long b = blockIdx.x;
+    const long long per = nblocks_padded >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// --------------------------------------------------------------------------
+// Collide-and-stream step.
+//   MODE_EVEN / MODE_ODD: in place on f (src == dst, padded layout).
+//   MODE_PUSH: canonical src -> canonical dst (local read, scattered write).
+// STATS: add u and u^2 of the pre-collision state into acc [6][N].
+// --------------------------------------------------------------------------
+template <int K, int MODE, bool STATS>
+__global__ void __launch_bounds__(256)
+k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
+       const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
+       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nblocks_padded)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long blk = xcd_block(nblocks_padded);
+    const long long wave = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int cx = (int)(wave % g.ncx);
+    const long long row = wave / g.ncx;
+    const int y = (int)(row % g.ny);
+    const int z = (int)(row / g.ny);
+    const int x = cx * 64 + lane;
+
+    // ---------------- uniform fast-path test ----------------
+    bool fast = (y >= 1) && (y <= g.ny - 2) && (z >= 1) && (z <= g.nz - 2) && (cx >= 1) && (cx * 64 + 63 <= g.nx - 2);
+    if (fast) {
+        uint64_t acc = 0;
+#pragma unroll
+        for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+            for (int dy = -1; dy <= 1; dy++) {
+                const uint64_t* w = mask + (long long)((y + dy) + (long long)g.ny * (z + dz)) * g.wpr + cx;
+                acc |= w[0] | (w[-1] >> 63) | (w[1] << 63);
+            }
+        fast = (acc == 0);
+    }
+
+    if (fast) {
+        const long long ns = cell_index(ls, g.ny, x, y, z);
+        const long long nd = cell_index(ld, g.ny, x, y, z);
+        R h[NQ];
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            long long idx;
+            if constexpr (MODE == MODE_ODD)
+                idx = (long long)opp(I) * ls.S + ns - (c.x + (long long)ls.pitch * (c.y + (long long)g.ny * c.z));
+            else
+                idx = (long long)I * ls.S + ns;
+            h[I] = C::dec(src[idx]);
+        });
+        R drho, ux, uy, uz, tau;
+        collide<R>(h, P, drho, ux, uy, uz, tau);
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            long long idx;
+            if constexpr (MODE == MODE_EVEN)
+                idx = (long long)I * ld.S + nd;
+            else
+                idx = (long long)opp(I) * ld.S + nd - (c.x + (long long)ld.pitch * (c.y + (long long)g.ny * c.z));
+            dst[idx] = C::enc(h[opp(I)]);
+        });
+        if constexpr (STATS) {
+            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+            stats[n] += ux;
+            stats[g.N + n] += uy;
+            stats[2 * g.N + n] += uz;
+            stats[3 * g.N + n] += ux * ux;
+            stats[4 * g.N + n] += uy * uy;
+            stats[5 * g.N + n] += uz * uz;
+        }
+        return;
+    }
+
+    // ---------------- general path: every boundary rule, per lane ----------------
+    if (x >= g.nx) return;
+    const long long ns = cell_index(ls, g.ny, x, y, z);
+    const long long nd = cell_index(ld, g.ny, x, y, z);
+    if (solid_at(mask, g, x, y, z)) {
+        if constexpr (MODE == MODE_PUSH) {
+            static_for<0, NQ>([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                dst[(long long)I * ld.S + nd] = C::enc(R(0));
+            });
+        }
+        return;
+    }
+    R h[NQ];
+    R ux, uy, uz;
+    const int inf = inflow_face_of(g, x, y, z);
+    if (inf >= 0) {
+        // inflow cell: post-collision state is feq(rho0, u_in(z)) whatever it held
+        load_profile<R>(prof, g.nz, inf, z, ux, uy, uz);
+        equilibrium_shifted<R>(P.rho0, R(0), ux, uy, uz, h);
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (MODE == MODE_EVEN) {
+                dst[(long long)I * ld.S + nd] = C::enc(h[opp(I)]);
+            } else if constexpr (MODE == MODE_PUSH) {
+                // canonical output of an inflow cell is its own equilibrium
+                dst[(long long)I * ld.S + nd] = C::enc(h[I]);
+                const Res r = resolve_plain<I>(g, mask, x, y, z);
+                if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
+                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::enc(h[opp(I)]);
+            } else {
+                const Res r = resolve_plain<I>(g, mask, x, y, z);
+                if (r.kind == 0)
+                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::enc(h[opp(I)]);
+            }
+        });
+    } else {
+        // gather
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (MODE == MODE_ODD) {
+                int qx, qy, qz, owner;
+                if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
+                    h[I] = C::dec(ghost[ghost_index<I>(g, owner, x, y, z)]);
+                } else {
+                    const Res r = resolve_plain<I>(g, mask, x, y, z);
+                    h[I] = C::dec(src[(long long)r.dir * ls.S + cell_index(ls, g.ny, r.x, r.y, r.z)]);
+                }
+            } else {
+                h[I] = C::dec(src[(long long)I * ls.S + ns]);
+            }
+        });
+        R drho, tau;
+        collide<R>(h, P, drho, ux, uy, uz, tau);
+        // scatter
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (MODE == MODE_EVEN) {
+                dst[(long long)I * ld.S + nd] = C::enc(h[opp(I)]);
+            } else {
+                int qx, qy, qz, owner;
+                if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
+                    // opp(I) leaves through the outflow face: kept only as the
+                    // bounce-back of a solid inner neighbour
+                    if (solid_at(mask, g, qx, qy, qz)) dst[(long long)I * ld.S + nd] = C::enc(h[opp(I)]);
+                } else {
+                    const Res r = resolve_plain<I>(g, mask, x, y, z);
+                    if (r.kind == 0) {
+                        if constexpr (MODE == MODE_PUSH) {
+                            if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
+                        }
+                        dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::enc(h[opp(I)]);
+                    }
+                }
+            }
+        });
+    }
+    if constexpr (STATS) {
+        const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+        stats[n] += ux;
+        stats[g.N + n] += uy;
+        stats[2 * g.N + n] += uz;
+        stats[3 * g.N + n] += ux * ux;
+        stats[4 * g.N + n] += uy * uy;
+        stats[5 * g.N + n] += uz * uz;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Zero-gradient outflow passes for one outflow face F.
+//   ghost: before an odd step, store for each (cell on F, entering direction
+//          owned by F) the value the inner cell q pulls (or the bounce-back
+//          when q is solid), read from the swapped layout.  The odd step
+//          reads these instead of slots its neighbours overwrite.
+//   copy:  after an odd step (natural layout), or after a push step,
+//          f_I(p) = f_I(q) for every such pair with q fluid.
+// --------------------------------------------------------------------------
+__device__ inline bool face_cell(const Geo& g, int F, long long t, int& x, int& y, int& z)
+{
+    const int a = F >> 1;
+    if (a == 0) {
+        if (t >= (long long)g.ny * g.nz) return false;
+        x = (F & 1) ? g.nx - 1 : 0; y = (int)(t % g.ny); z = (int)(t / g.ny);
+    } else if (a == 1) {
+        if (t >= (long long)g.nx * g.nz) return false;
+        y = (F & 1) ? g.ny - 1 : 0; x = (int)(t % g.nx); z = (int)(t / g.nx);
+    } else {
+        if (t >= (long long)g.nx * g.ny) return false;
+        z = (F & 1) ? g.nz - 1 : 0; x = (int)(t % g.nx); y = (int)(t / g.nx);
+    }
+    return true;
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_outflow_ghost(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, typename Codec<K>::store* ghost,
+                Geo g, Lay L, int F)
+{
+    int x, y, z;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (!face_cell(g, F, t, x, y, z)) return;
+    if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) return;
+    static_for<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        int qx, qy, qz, owner;
+        if (!outflow_entering<I>(g, x, y, z, qx, qy, qz, owner) || owner != F) return;
+        typename Codec<K>::store v;
+        if (solid_at(mask, g, qx, qy, qz)) {
+            v = f[(long long)I * L.S + cell_index(L, g.ny, x, y, z)];
+        } else {
+            const Res r = resolve_plain<I>(g, mask, qx, qy, qz);
+            v = f[(long long)r.dir * L.S + cell_index(L, g.ny, r.x, r.y, r.z)];
+        }
+        ghost[ghost_index<I>(g, F, x, y, z)] = v;
+    });
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_outflow_copy(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, Geo g, Lay L, int F)
+{
+    int x, y, z;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (!face_cell(g, F, t, x, y, z)) return;
+    if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) return;
+    static_for<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        int qx, qy, qz, owner;
+        if (!outflow_entering<I>(g, x, y, z, qx, qy, qz, owner) || owner != F) return;
+        if (solid_at(mask, g, qx, qy, qz)) return;
+        f[(long long)I * L.S + cell_index(L, g.ny, x, y, z)] = f[(long long)I * L.S + cell_index(L, g.ny, qx, qy, qz)];
+    });
+}
+
+// --------------------------------------------------------------------------
+// Populations of one cell in the current state (phase 0: natural layout,
+// phase 1: swapped layout after an even step, resolved through the full
+// streaming rules).  Cell must be fluid and not an inflow cell.
+// --------------------------------------------------------------------------
+template <int K>
+__device__ inline void load_cell(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const Geo& g,
+                                 const Lay& L, int phase, int x, int y, int z, typename Codec<K>::store* out)
+{
+    static_for<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if (phase == 0) {
+            out[I] = f[(long long)I * L.S + cell_index(L, g.ny, x, y, z)];
+        } else {
+            const Res r = resolve_full<I>(g, mask, x, y, z);
+            out[I] = f[(long long)r.dir * L.S + cell_index(L, g.ny, r.x, r.y, r.z)];
+        }
+    });
+}
+
+// Initial state: feq(rho0, u0(z) + noise) in fluid cells (double precision,
+// then encoded), 0 in solid cells and padding.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_init(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+       const double* __restrict__ u0, Geo g, Lay L, double rho0, double amp, uint64_t seed)
+{
+    using C = Codec<K>;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long cells = (long long)L.pitch * g.ny * g.nz;
+    if (t >= cells) return;
+    const int x = (int)(t % L.pitch);
+    const long long row = t / L.pitch;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    double h[NQ];
+    for (int i = 0; i < NQ; i++) h[i] = 0.0;
+    if (x < g.nx && !solid_at(mask, g, x, y, z)) {
+        double u[3];
+        const int inf = inflow_face_of(g, x, y, z);
+        if (inf >= 0) {
+            load_profile<double>(prof, g.nz, inf, z, u[0], u[1], u[2]);
+        } else {
+            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+            for (int c = 0; c < 3; c++) {
+                const uint64_t r = splitmix64(seed + 3ull * (uint64_t)n + (uint64_t)c);
+                const double unit = (double)(r >> 11) * (1.0 / 9007199254740992.0);
+                u[c] = u0[3 * z + c] + amp * (2.0 * unit - 1.0);
+            }
+        }
+        equilibrium_shifted<double>(rho0, 0.0, u[0], u[1], u[2], h);
+    }
+    for (int i = 0; i < NQ; i++) f[(long long)i * L.S + t] = C::enc((typename C::real)h[i]);
+}
+
+// Canonical export: dst[i][n] = h_i(x, t) (unpadded), inflow cells at their
+// equilibrium, solid cells 0.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_export(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+         Geo g, Lay L, Phys<typename Codec<K>::real> P, int phase, typename Codec<K>::store* dst)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const int x = (int)(n % g.nx);
+    const long long row = n / g.nx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    typename C::store v[NQ];
+    if (solid_at(mask, g, x, y, z)) {
+        for (int i = 0; i < NQ; i++) v[i] = C::enc(R(0));
+    } else {
+        const int inf = inflow_face_of(g, x, y, z);
+        if (inf >= 0) {
+            R u[3], heq[NQ];
+            load_profile<R>(prof, g.nz, inf, z, u[0], u[1], u[2]);
+            equilibrium_shifted<R>(P.rho0, R(0), u[0], u[1], u[2], heq);
+            for (int i = 0; i < NQ; i++) v[i] = C::enc(heq[i]);
+        } else {
+            load_cell<K>(f, mask, g, L, phase, x, y, z, v);
+        }
+    }
+    for (int i = 0; i < NQ; i++) dst[(long long)i * g.N + n] = v[i];
+}
+
+// Canonical import into the natural layout (phase 0).
+template <int K>
+__global__ void __launch_bounds__(256)
+k_import(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, Geo g, Lay L,
+         const typename Codec<K>::store* src)
+{
+    using C = Codec<K>;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long cells = (long long)L.pitch * g.ny * g.nz;
+    if (t >= cells) return;
+    const int x = (int)(t % L.pitch);
+    const long long row = t / L.pitch;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const bool live = x < g.nx && !solid_at(mask, g, x, y, z) && inflow_face_of(g, x, y, z) < 0;
+    const long long n = x + (long long)g.nx * row;
+    for (int i = 0; i < NQ; i++)
+        f[(long long)i * L.S + t] = live ? src[(long long)i * g.N + n] : C::enc(typename C::real(0));
+}
+
+// Macroscopic fields (rho, u, nu_t = (tau_eff - tau0)/3) of the current state.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_macros(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+         Geo g, Lay L, Phys<typename Codec<K>::real> P, int phase, typename Codec<K>::real* rho,
+         typename Codec<K>::real* u, typename Codec<K>::real* nut)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const int x = (int)(n % g.nx);
+    const long long row = n / g.nx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    R r = P.rho0, ux = 0, uy = 0, uz = 0, nt = 0;
+    if (!solid_at(mask, g, x, y, z)) {
+        const int inf = inflow_face_of(g, x, y, z);
+        if (inf >= 0) {
+            load_profile<R>(prof, g.nz, inf, z, ux, uy, uz);
+        } else {
+            typename C::store v[NQ];
+            load_cell<K>(f, mask, g, L, phase, x, y, z, v);
+            R h[NQ];
+            for (int i = 0; i < NQ; i++) h[i] = C::dec(v[i]);
+            R drho, tau;
+            collide<R>(h, P, drho, ux, uy, uz, tau);
+            r = P.rho0 + drho;
+            nt = (tau - P.tau0) / R(3);
+        }
+    }
+    if (rho) rho[n] = r;
+    if (u) {
+        u[n] = ux;
+        u[g.N + n] = uy;
+        u[2 * g.N + n] = uz;
+    }
+    if (nut) nut[n] = nt;
+}
+
+// rho and u of one cell for probes (solid: rho0, 0; inflow: rho0, u_in).
+template <int K>
+__device__ inline void cell_rho_u(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask,
+                                  const double* __restrict__ prof, const Geo& g, const Lay& L,
+                                  const Phys<typename Codec<K>::real>& P, int phase, int x, int y, int z,
+                                  typename Codec<K>::real* out)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    out[0] = P.rho0;
+    out[1] = out[2] = out[3] = R(0);
+    if (solid_at(mask, g, x, y, z)) return;
+    const int inf = inflow_face_of(g, x, y, z);
+    if (inf >= 0) {
+        load_profile<R>(prof, g.nz, inf, z, out[1], out[2], out[3]);
+        return;
+    }
+    typename C::store v[NQ];
+    load_cell<K>(f, mask, g, L, phase, x, y, z, v);
+    R h[NQ];
+    for (int i = 0; i < NQ; i++) h[i] = C::dec(v[i]);
+    R drho, inv_rho;
+    moments<R>(h, P, drho, out[1], out[2], out[3], inv_rho);
+    out[0] = P.rho0 + drho;
+}
+
+template <int K>
+__global__ void k_probe_points(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask,
+                               const double* __restrict__ prof, Geo g, Lay L, Phys<typename Codec<K>::real> P,
+                               int phase, const float* pts, int np, float* out)
+{
+    using R = typename Codec<K>::real;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    float c[3] = {pts[3 * p], pts[3 * p + 1], pts[3 * p + 2]};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    int i0[3];
+    float fr[3];
+    for (int a = 0; a < 3; a++) {
+        float v = fminf(fmaxf(c[a], 0.0f), float(n[a] - 1));
+        int b = (int)floorf(v);
+        if (b > n[a] - 1) b = n[a] - 1;
+        i0[a] = b;
+        fr[a] = v - float(b);
+    }
+    R acc[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 8; k++) {
+        const int d[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+        R w = 1;
+        int q[3];
+        for (int a = 0; a < 3; a++) {
+            w *= d[a] ? R(fr[a]) : R(1) - R(fr[a]);
+            q[a] = min(i0[a] + d[a], n[a] - 1);
+        }
+        if (w == R(0)) continue;
+        R v[4];
+        cell_rho_u<K>(f, mask, prof, g, L, P, phase, q[0], q[1], q[2], v);
+        for (int j = 0; j < 4; j++) acc[j] += w * v[j];
+    }
+    for (int j = 0; j < 4; j++) out[4 * p + j] = float(acc[j]);
+}
+
+template <int K>
+__global__ void k_probe_cells(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask,
+                              const double* __restrict__ prof, Geo g, Lay L, Phys<typename Codec<K>::real> P,
+                              int phase, const int* cells, int np, typename Codec<K>::real* acc)
+{
+    using R = typename Codec<K>::real;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    R v[4];
+    cell_rho_u<K>(f, mask, prof, g, L, P, phase, cells[3 * p], cells[3 * p + 1], cells[3 * p + 2], v);
+    acc[3 * p] += v[1];
+    acc[3 * p + 1] += v[2];
+    acc[3 * p + 2] += v[3];
+}
+
+// --------------------------------------------------------------------------
+// Mass / energy / watchdog reduction over fluid, non-inflow cells.
+// Pass 1: per lane a Neumaier-compensated sum of rho - rho0 in the real
+// type and double sums of the kinetic energy, plus max |u|^2, max |rho-rho0|
+// and a non-finite flag; then a fixed-order double tree over the block.
+// Pass 2: one block reduces the block partials in a fixed order.
+// --------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS)
+k_mass_partial(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, Geo g, Lay L,
+               Phys<typename Codec<K>::real> P, int phase, double* partial)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    R s = 0, comp = 0;
+    double e = 0, umax = 0, dmax = 0, bad = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < g.N; n += stride) {
+        const int x = (int)(n % g.nx);
+        const long long row = n / g.nx;
+        const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+        if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) continue;
+        typename C::store v[NQ];
+        load_cell<K>(f, mask, g, L, phase, x, y, z, v);
+        R h[NQ];
+        for (int i = 0; i < NQ; i++) h[i] = C::dec(v[i]);
+        R drho, ux, uy, uz, inv_rho;
+        moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+        // Neumaier summation of drho
+        const R tsum = s + drho;
+        if (fabs((double)s) >= fabs((double)drho)) comp += (s - tsum) + drho;
+        else comp += (drho - tsum) + s;
+        s = tsum;
+        const double rho = (double)P.rho0 + (double)drho;
+        const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        e += 0.5 * rho * u2;
+        if (!(u2 <= 1e300) || !(fabs((double)drho) <= 1e300)) bad = 1;
+        umax = fmax(umax, u2);
+        dmax = fmax(dmax, fabs((double)drho));
+    }
+    __shared__ double sh[5][RED_THREADS];
+    sh[0][threadIdx.x] = (double)s + (double)comp;
+    sh[1][threadIdx.x] = e;
+    sh[2][threadIdx.x] = umax;
+    sh[3][threadIdx.x] = dmax;
+    sh[4][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + w]);
+            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + w]);
+            sh[4][threadIdx.x] = fmax(sh[4][threadIdx.x], sh[4][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; k++) partial[5 * blockIdx.x + k] = sh[k][0];
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_mass_final(const double* partial, int nb, double* out)
+{
+    __shared__ double sh[5][RED_THREADS];
+    double a[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) {
+        a[0] += partial[5 * b];
+        a[1] += partial[5 * b + 1];
+        a[2] = fmax(a[2], partial[5 * b + 2]);
+        a[3] = fmax(a[3], partial[5 * b + 3]);
+        a[4] = fmax(a[4], partial[5 * b + 4]);
+    }
+    for (int k = 0; k < 5; k++) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+            for (int k = 2; k < 5; k++) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; k++) out[k] = sh[k][0];
+}
+
+// --------------------------------------------------------------------------
+// Host launchers
+// --------------------------------------------------------------------------
+template <int K>
+static Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
+{
+    using R = typename Codec<K>::real;
+    Phys<R> P;
+    P.tau0 = R(d.tau0);
+    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
+    P.rho0 = R(d.rho0);
+    for (int a = 0; a < 3; a++) P.F[a] = R(d.force[a]);
+    P.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+    return P;
+}
+
+static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int K, int MODE, bool ST>
+static hipError_t step_k(const DevCtx& d, const void* src, void* dst, Lay ls, Lay ld, void* stats, hipStream_t s)
+{
+    using C = Codec<K>;
+    const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
+    const long long nb = (nwaves + 3) / 4;
+    const long long nbp = (nb + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_step<K, MODE, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)dst,
+                       (const typename C::store*)src, d.mask, d.prof, (const typename C::store*)d.ghost, d.g, ls, ld,
+                       phys_of<K>(d), (typename C::real*)stats, nwaves, nbp);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t step_dispatch(const DevCtx& d, int mode, const void* src, void* dst, Lay ls, Lay ld, void* stats,
+                                hipStream_t s)
+{
+    if (mode == MODE_EVEN) return stats ? step_k<K, MODE_EVEN, true>(d, src, dst, ls, ld, stats, s)
+                                        : step_k<K, MODE_EVEN, false>(d, src, dst, ls, ld, stats, s);
+    if (mode == MODE_ODD) return stats ? step_k<K, MODE_ODD, true>(d, src, dst, ls, ld, stats, s)
+                                       : step_k<K, MODE_ODD, false>(d, src, dst, ls, ld, stats, s);
+    return step_k<K, MODE_PUSH, false>(d, src, dst, ls, ld, nullptr, s);
+}
+
+#define LBM_DISPATCH(codec, CALL)              \
+    switch (codec) {                           \
+        case 0: { constexpr int K = 0; CALL; } \
+        case 1: { constexpr int K = 1; CALL; } \
+        case 2: { constexpr int K = 2; CALL; } \
+        case 3: { constexpr int K = 3; CALL; } \
+        default: return hipErrorInvalidValue;  \
+    }
+
+static Lay padded(const DevCtx& d) { return Lay{d.g.S, d.g.pitch}; }
+static Lay canonical(const DevCtx& d) { return Lay{d.g.N, d.g.nx}; }
+
+hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, return step_dispatch<K>(d, odd ? MODE_ODD : MODE_EVEN, d.f, d.f, padded(d), padded(d), stats, s));
+}
+
+hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, {
+        hipError_t e = step_dispatch<K>(d, MODE_PUSH, src, dst, canonical(d), canonical(d), nullptr, s);
+        if (e != hipSuccess) return e;
+        return launch_outflow_copy(d, dst, 1, s);
+    });
+}
+
+static long long face_cells(const Geo& g, int F)
+{
+    const int a = F >> 1;
+    return a == 0 ? (long long)g.ny * g.nz : (a == 1 ? (long long)g.nx * g.nz : (long long)g.nx * g.ny);
+}
+
+hipError_t launch_outflow_ghost(const DevCtx& d, hipStream_t s)
+{
+    for (int F = 0; F < 6; F++) {
+        if (d.g.face[F] != F_OUTFLOW) continue;
+        const long long fc = face_cells(d.g, F);
+        LBM_DISPATCH(d.codec, {
+            hipLaunchKernelGGL((k_outflow_ghost<K>), dim3(blocks_for(fc, 256)), dim3(256), 0, s,
+                               (const typename Codec<K>::store*)d.f, d.mask, (typename Codec<K>::store*)d.ghost, d.g,
+                               padded(d), F);
+            break;
+        });
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_outflow_copy(const DevCtx& d, void* arr, int canonical_layout, hipStream_t s)
+{
+    const Lay L = canonical_layout ? canonical(d) : padded(d);
+    for (int F = 0; F < 6; F++) {
+        if (d.g.face[F] != F_OUTFLOW) continue;
+        const long long fc = face_cells(d.g, F);
+        LBM_DISPATCH(d.codec, {
+            hipLaunchKernelGGL((k_outflow_copy<K>), dim3(blocks_for(fc, 256)), dim3(256), 0, s,
+                               (typename Codec<K>::store*)arr, d.mask, d.g, L, F);
+            break;
+        });
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const DevCtx& d, const double* u0_dev, double amp, uint64_t seed, hipStream_t s)
+{
+    const long long cells = (long long)d.g.pitch * d.g.ny * d.g.nz;
+    LBM_DISPATCH(d.codec, {
+        hipLaunchKernelGGL((k_init<K>), dim3(blocks_for(cells, 256)), dim3(256), 0, s, (typename Codec<K>::store*)d.f,
+                           d.mask, d.prof, u0_dev, d.g, padded(d), d.rho0, amp, seed);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_export(const DevCtx& d, int phase, void* dst, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, {
+        hipLaunchKernelGGL((k_export<K>), dim3(blocks_for(d.g.N, 256)), dim3(256), 0, s,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           (typename Codec<K>::store*)dst);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_import(const DevCtx& d, const void* src, hipStream_t s)
+{
+    const long long cells = (long long)d.g.pitch * d.g.ny * d.g.nz;
+    LBM_DISPATCH(d.codec, {
+        hipLaunchKernelGGL((k_import<K>), dim3(blocks_for(cells, 256)), dim3(256), 0, s,
+                           (typename Codec<K>::store*)d.f, d.mask, d.g, padded(d), (const typename Codec<K>::store*)src);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_macros(const DevCtx& d, int phase, void* rho, void* u, void* nut, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, {
+        using R = typename Codec<K>::real;
+        hipLaunchKernelGGL((k_macros<K>), dim3(blocks_for(d.g.N, 256)), dim3(256), 0, s,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           (R*)rho, (R*)u, (R*)nut);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_probe_points(const DevCtx& d, int phase, const float* pts, int np, float* out, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, {
+        hipLaunchKernelGGL((k_probe_points<K>), dim3(blocks_for(np, 64)), dim3(64), 0, s,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           pts, np, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_probe_cells(const DevCtx& d, int phase, const int* cells, int np, void* acc, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, {
+        using R = typename Codec<K>::real;
+        hipLaunchKernelGGL((k_probe_cells<K>), dim3(blocks_for(np, 64)), dim3(64), 0, s,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           cells, np, (R*)acc);
+        return hipGetLastError();
+    });
+}
+
+int mass_blocks(const Geo& g)
+{
+    long long nb = (g.N + RED_THREADS - 1) / RED_THREADS;
+    return (int)(nb < 2048 ? nb : 2048);
+}
+
+hipError_t launch_mass(const DevCtx& d, int phase, double* partial, double* out5, hipStream_t s)
+{
+    const int nb = mass_blocks(d.g);
+    LBM_DISPATCH(d.codec, {
+        hipLaunchKernelGGL((k_mass_partial<K>), dim3(nb), dim3(RED_THREADS), 0, s,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.g, padded(d), phys_of<K>(d), phase, partial);
+        hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(RED_THREADS), 0, s, partial, nb, out5);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace lbm

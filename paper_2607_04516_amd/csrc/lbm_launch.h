@@ -1,0 +1,37 @@
+// Internal interface between the C-ABI runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Everything a kernel launch needs to know about one context.
+struct DevCtx {
+    Geo g;
+    int codec;            // 0 F64, 1 F32, 2 F16S, 3 BF16S
+    void* f;              // in-place population array [19][nz][ny][pitch]
+    const uint64_t* mask; // solid bits [nz][ny][wpr]
+    void* ghost;          // outflow ghost entries
+    const double* prof;   // inflow profiles [6][nz][3]
+    double tau0, c_smag, delta, rho0, force[3];
+};
+
+hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s);
+hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s);
+hipError_t launch_outflow_ghost(const DevCtx& d, hipStream_t s);
+hipError_t launch_outflow_copy(const DevCtx& d, void* arr, int canonical_layout, hipStream_t s);
+hipError_t launch_init(const DevCtx& d, const double* u0_dev, double amp, uint64_t seed, hipStream_t s);
+hipError_t launch_export(const DevCtx& d, int phase, void* dst, hipStream_t s);
+hipError_t launch_import(const DevCtx& d, const void* src, hipStream_t s);
+hipError_t launch_macros(const DevCtx& d, int phase, void* rho, void* u, void* nut, hipStream_t s);
+hipError_t launch_probe_points(const DevCtx& d, int phase, const float* pts, int np, float* out, hipStream_t s);
+hipError_t launch_probe_cells(const DevCtx& d, int phase, const int* cells, int np, void* acc, hipStream_t s);
+int mass_blocks(const Geo& g);
+hipError_t launch_mass(const DevCtx& d, int phase, double* partial, double* out5, hipStream_t s);
+hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
+                          int np, const void* probe_src, void* g_inflow, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,545 @@
+// C-ABI runtime of the D3Q19 LBM-LES library: context lifetime, argument
+// validation, device allocation, parity bookkeeping of the in-place A-A
+// update, error reporting.  Declarations and contracts are in include/lbm.h.
+#include "lbm.h"
+#include "lbm_launch.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lbm;
+
+struct lbm_ctx {
+    DevCtx d;
+    lbm_params p;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int phase = 0;          // 0: natural layout (pre-collision f(t)); 1: swapped (after an even step)
+    int64_t t = 0;
+    size_t store_bytes = 0; // bytes of one stored population
+    void* f = nullptr;
+    uint64_t* mask = nullptr;
+    void* ghost = nullptr;
+    double* prof = nullptr; // device [6][nz][3]
+    std::vector<double> prof_host;
+    bool prof_set[6] = {false, false, false, false, false, false};
+    double* u0 = nullptr;   // device [nz][3] scratch for initialisation
+    int* probes = nullptr;  // device [np][3]
+    int np = 0;
+    double* red_partial = nullptr;
+    double* red_out = nullptr;  // device [5]
+    void* stats = nullptr;
+    int stats_stride = 0;
+    int64_t fluid = 0, interior = 0;
+    // step-kernel timing (lbm_profile): event pairs around each launch
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    std::string err;
+};
+
+static thread_local std::string g_create_error;
+
+static int fail(lbm_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+static int hip_fail(lbm_ctx* c, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, LBM_EHIP, m);
+}
+
+#define HIPCHK(ctx, expr, what)                          \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+    } while (0)
+
+static size_t codec_bytes(int s)
+{
+    switch (s) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16S:
+        case LBM_BF16S: return 2;
+        default: return 0;
+    }
+}
+
+static long long face_cells_host(const Geo& g, int F)
+{
+    const int a = F >> 1;
+    return a == 0 ? (long long)g.ny * g.nz : (a == 1 ? (long long)g.nx * g.nz : (long long)g.nx * g.ny);
+}
+
+static void free_all(lbm_ctx* c)
+{
+    if (!c) return;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    c->ev_used = 0;
+    void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    c->f = nullptr;
+    c->mask = nullptr;
+    c->ghost = nullptr;
+    c->prof = nullptr;
+    c->u0 = nullptr;
+    c->probes = nullptr;
+    c->red_partial = nullptr;
+    c->red_out = nullptr;
+}
+
+static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
+{
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 8);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return fail(c, LBM_ENOMEM, std::string("out of device memory allocating ") + what);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    return LBM_OK;
+}
+
+static int upload_u0(lbm_ctx* c, const double* u0)
+{
+    const int nz = c->d.g.nz;
+    std::vector<double> h(3 * (size_t)nz);
+    for (int z = 0; z < nz; z++)
+        for (int a = 0; a < 3; a++) h[3 * z + a] = u0 ? u0[3 * z + a] : c->p.u_init[a];
+    HIPCHK(c, hipMemcpyAsync(c->u0, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream), "upload u0");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "upload u0");
+    return LBM_OK;
+}
+
+extern "C" {
+
+int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* params, lbm_ctx** out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grid || !solid || !params) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (grid->nx < 3 || grid->ny < 3 || grid->nz < 3) return fail(nullptr, LBM_EINVAL, "each dimension must be >= 3");
+    if (!(params->tau0 > 0.5) || !std::isfinite(params->tau0)) return fail(nullptr, LBM_EINVAL, "tau0 must be > 1/2");
+    if (!(params->c_smag >= 0.0) || !(params->delta > 0.0) || !(params->rho0 > 0.0))
+        return fail(nullptr, LBM_EINVAL, "c_smag must be >= 0, delta and rho0 > 0");
+    if (codec_bytes(params->storage) == 0) return fail(nullptr, LBM_EINVAL, "unknown storage codec");
+    for (int a = 0; a < 3; a++) {
+        const int lo = params->face[2 * a], hi = params->face[2 * a + 1];
+        if (lo < 0 || lo > 4 || hi < 0 || hi > 4) return fail(nullptr, LBM_EINVAL, "unknown face kind");
+        if ((lo == LBM_PERIODIC) != (hi == LBM_PERIODIC)) return fail(nullptr, LBM_EINVAL, "periodic faces must be paired");
+    }
+    const long long N = (long long)grid->nx * grid->ny * grid->nz;
+    if (N > (1ll << 40)) return fail(nullptr, LBM_EINVAL, "grid too large");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+    c->p = *params;
+    c->stream = (hipStream_t)params->hip_stream;
+    c->store_bytes = codec_bytes(params->storage);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBM_EHIP, "no HIP device");
+    }
+
+    Geo& g = c->d.g;
+    g.nx = grid->nx;
+    g.ny = grid->ny;
+    g.nz = grid->nz;
+    g.ncx = (g.nx + 63) / 64;
+    g.pitch = g.ncx * 64;
+    g.wpr = g.ncx;
+    for (int k = 0; k < 6; k++) g.face[k] = params->face[k];
+    g.S = (long long)g.pitch * g.ny * g.nz;
+    g.N = N;
+    long long goff = 0;
+    for (int F = 0; F < 6; F++) {
+        g.ghost_off[F] = goff;
+        if (g.face[F] == LBM_OUTFLOW_ZG) goff += 5 * face_cells_host(g, F);
+    }
+    c->d.codec = params->storage;
+    c->d.tau0 = params->tau0;
+    c->d.c_smag = params->c_smag;
+    c->d.delta = params->delta;
+    c->d.rho0 = params->rho0;
+    for (int a = 0; a < 3; a++) c->d.force[a] = params->body_force[a];
+
+    // bit-packed solid mask, cell counts
+    std::vector<uint64_t> bits((size_t)g.wpr * g.ny * g.nz, 0ull);
+    auto is_inflow = [&](int x, int y, int z) {
+        return (g.face[0] == LBM_INFLOW_EQ && x == 0) || (g.face[1] == LBM_INFLOW_EQ && x == g.nx - 1) ||
+               (g.face[2] == LBM_INFLOW_EQ && y == 0) || (g.face[3] == LBM_INFLOW_EQ && y == g.ny - 1) ||
+               (g.face[4] == LBM_INFLOW_EQ && z == 0) || (g.face[5] == LBM_INFLOW_EQ && z == g.nz - 1);
+    };
+    for (int z = 0; z < g.nz; z++)
+        for (int y = 0; y < g.ny; y++)
+            for (int x = 0; x < g.nx; x++) {
+                const size_t n = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
+                if (solid[n]) {
+                    bits[((size_t)y + (size_t)g.ny * z) * g.wpr + (x >> 6)] |= 1ull << (x & 63);
+                } else {
+                    c->fluid++;
+                    if (!is_inflow(x, y, z)) c->interior++;
+                }
+            }
+
+    int rc;
+    const size_t pop_bytes = (size_t)NQ * (size_t)g.S * c->store_bytes;
+    if ((rc = device_alloc(c, &c->f, pop_bytes, "populations")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->mask, bits.size() * sizeof(uint64_t), "mask")) != LBM_OK ||
+        (rc = device_alloc(c, &c->ghost, (size_t)goff * c->store_bytes, "ghost planes")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->prof, 18 * (size_t)g.nz * sizeof(double), "profiles")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->u0, 3 * (size_t)g.nz * sizeof(double), "u0")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->red_partial, 5 * (size_t)mass_blocks(g) * sizeof(double), "reduction")) !=
+            LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->red_out, 8 * sizeof(double), "reduction")) != LBM_OK) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    c->prof_host.assign(18 * (size_t)g.nz, 0.0);
+    hipError_t e = hipMemcpy(c->mask, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->prof, 0, 18 * (size_t)g.nz * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(c->f, 0, pop_bytes);
+    if (e == hipSuccess && goff) e = hipMemset(c->ghost, 0, (size_t)goff * c->store_bytes);
+    if (e != hipSuccess) {
+        hip_fail(nullptr, e, "upload");
+        free_all(c);
+        delete c;
+        return LBM_EHIP;
+    }
+    c->d.f = c->f;
+    c->d.mask = c->mask;
+    c->d.ghost = c->ghost;
+    c->d.prof = c->prof;
+    if ((rc = lbm_reset(c, nullptr)) != LBM_OK) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+const char* lbm_last_error(const lbm_ctx* c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+int lbm_cell_counts(const lbm_ctx* c, int64_t* fluid, int64_t* interior)
+{
+    if (!c) return LBM_EINVAL;
+    if (fluid) *fluid = c->fluid;
+    if (interior) *interior = c->interior;
+    return LBM_OK;
+}
+
+int lbm_set_stream(lbm_ctx* c, void* s)
+{
+    if (!c) return LBM_EINVAL;
+    c->stream = (hipStream_t)s;
+    c->p.hip_stream = s;
+    return LBM_OK;
+}
+
+int lbm_set_inflow(lbm_ctx* c, int32_t face, const double* u)
+{
+    if (!c) return LBM_EINVAL;
+    if (face < 0 || face > 5 || !u) return fail(c, LBM_EINVAL, "bad face or NULL profile");
+    if (c->d.g.face[face] != LBM_INFLOW_EQ) return fail(c, LBM_EINVAL, "face is not an INFLOW_EQ face");
+    const int nz = c->d.g.nz;
+    for (int i = 0; i < 3 * nz; i++) {
+        if (!std::isfinite(u[i])) return fail(c, LBM_EINVAL, "non-finite inflow velocity");
+        c->prof_host[(size_t)face * 3 * nz + i] = u[i];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->prof + (size_t)face * 3 * nz, c->prof_host.data() + (size_t)face * 3 * nz,
+                             3 * (size_t)nz * sizeof(double), hipMemcpyHostToDevice, c->stream),
+           "upload inflow profile");
+    // the host copy must stay valid until the copy ran
+    HIPCHK(c, hipStreamSynchronize(c->stream), "upload inflow profile");
+    c->prof_set[face] = true;
+    return LBM_OK;
+}
+
+int lbm_reset(lbm_ctx* c, const double* u0)
+{
+    if (!c) return LBM_EINVAL;
+    int rc = upload_u0(c, u0);
+    if (rc != LBM_OK) return rc;
+    HIPCHK(c, launch_init(c->d, c->u0, c->p.noise_amp, c->p.noise_seed, c->stream), "init kernel");
+    c->phase = 0;
+    c->t = 0;
+    return LBM_OK;
+}
+
+static int check_ready(lbm_ctx* c)
+{
+    for (int F = 0; F < 6; F++)
+        if (c->d.g.face[F] == LBM_INFLOW_EQ && !c->prof_set[F])
+            return fail(c, LBM_ESTATE, "inflow face " + std::to_string(F) + " has no profile (lbm_set_inflow)");
+    return LBM_OK;
+}
+
+static bool has_outflow(const lbm_ctx* c)
+{
+    for (int F = 0; F < 6; F++)
+        if (c->d.g.face[F] == LBM_OUTFLOW_ZG) return true;
+    return false;
+}
+
+static int mark(lbm_ctx* c)
+{
+    if (!c->profiling) return LBM_OK;
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e), "event create");
+        c->ev.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream), "event record");
+    return LBM_OK;
+}
+
+static int one_step(lbm_ctx* c)
+{
+    void* st = nullptr;
+    int rc;
+    if (c->stats && c->stats_stride > 0 && (c->t % c->stats_stride) == 0) st = c->stats;
+    if (c->phase == 0) {
+        if ((rc = mark(c)) != LBM_OK) return rc;
+        HIPCHK(c, launch_step(c->d, 0, st, c->stream), "even step");
+        if ((rc = mark(c)) != LBM_OK) return rc;
+        c->phase = 1;
+    } else {
+        const bool out = has_outflow(c);
+        if (out) HIPCHK(c, launch_outflow_ghost(c->d, c->stream), "outflow ghost");
+        if ((rc = mark(c)) != LBM_OK) return rc;
+        HIPCHK(c, launch_step(c->d, 1, st, c->stream), "odd step");
+        if ((rc = mark(c)) != LBM_OK) return rc;
+        if (out) HIPCHK(c, launch_outflow_copy(c->d, c->f, 0, c->stream), "outflow copy");
+        c->phase = 0;
+    }
+    c->t += 1;
+    return LBM_OK;
+}
+
+static int reduce(lbm_ctx* c, double out[5])
+{
+    HIPCHK(c, launch_mass(c->d, c->phase, c->red_partial, c->red_out, c->stream), "mass reduction");
+    HIPCHK(c, hipMemcpyAsync(out, c->red_out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "mass copy");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "mass sync");
+    return LBM_OK;
+}
+
+static int watchdog(lbm_ctx* c)
+{
+    double r[5];
+    int rc = reduce(c, r);
+    if (rc != LBM_OK) return rc;
+    if (r[4] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1]) || !(r[2] <= 0.25) || !(r[3] <= 0.5)) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "unstable at t=%lld: max|u|^2=%g max|rho-rho0|=%g nonfinite=%g", (long long)c->t,
+                 r[2], r[3], r[4]);
+        return fail(c, LBM_EUNSTABLE, buf);
+    }
+    return LBM_OK;
+}
+
+static int step_n(lbm_ctx* c, int64_t n, void* acc)
+{
+    if (!c) return LBM_EINVAL;
+    if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+    if (acc && c->np == 0) return fail(c, LBM_ESTATE, "no probes registered");
+    int rc = check_ready(c);
+    if (rc != LBM_OK) return rc;
+    const int wd = c->p.watchdog_stride;
+    for (int64_t k = 0; k < n; k++) {
+        if ((rc = one_step(c)) != LBM_OK) return rc;
+        if (acc) HIPCHK(c, launch_probe_cells(c->d, c->phase, c->probes, c->np, acc, c->stream), "probe accumulate");
+        if (wd > 0 && (c->t % wd) == 0 && (rc = watchdog(c)) != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) { return step_n(c, n, nullptr); }
+
+int lbm_step_probed(lbm_ctx* c, int64_t n, void* acc)
+{
+    if (!acc) return fail(c, LBM_EINVAL, "NULL accumulator");
+    return step_n(c, n, acc);
+}
+
+int lbm_macros(lbm_ctx* c, void* rho, void* u, void* nut)
+{
+    if (!c) return LBM_EINVAL;
+    if (!rho && !u && !nut) return LBM_OK;
+    HIPCHK(c, launch_macros(c->d, c->phase, rho, u, nut, c->stream), "macros kernel");
+    return LBM_OK;
+}
+
+int lbm_probe(lbm_ctx* c, const float* pts, int32_t np, float* out)
+{
+    if (!c) return LBM_EINVAL;
+    if (np < 0 || (np > 0 && (!pts || !out))) return fail(c, LBM_EINVAL, "bad probe arguments");
+    if (np == 0) return LBM_OK;
+    for (int i = 0; i < 3 * np; i++)
+        if (!std::isfinite(pts[i])) return fail(c, LBM_EINVAL, "non-finite probe coordinate");
+    float* dbuf = nullptr;
+    int rc = device_alloc(c, (void**)&dbuf, (size_t)np * 7 * sizeof(float), "probe buffer");
+    if (rc != LBM_OK) return rc;
+    hipError_t e = hipMemcpyAsync(dbuf, pts, (size_t)np * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_probe_points(c->d, c->phase, dbuf, np, dbuf + 3 * (size_t)np, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, dbuf + 3 * (size_t)np, (size_t)np * 4 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dbuf);
+    if (e != hipSuccess) return hip_fail(c, e, "probe");
+    return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx* c, double* mass, double* energy)
+{
+    if (!c) return LBM_EINVAL;
+    double r[5];
+    int rc = reduce(c, r);
+    if (rc != LBM_OK) return rc;
+    if (mass) *mass = (double)c->interior * c->p.rho0 + r[0];
+    if (energy) *energy = r[1];
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* c, void* dst, int64_t* t)
+{
+    if (!c) return LBM_EINVAL;
+    if (!dst) return fail(c, LBM_EINVAL, "NULL destination");
+    HIPCHK(c, launch_export(c->d, c->phase, dst, c->stream), "export kernel");
+    if (t) *t = c->t;
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const void* src, int64_t t)
+{
+    if (!c) return LBM_EINVAL;
+    if (!src || t < 0) return fail(c, LBM_EINVAL, "NULL source or negative time");
+    HIPCHK(c, launch_import(c->d, src, c->stream), "import kernel");
+    c->phase = 0;
+    c->t = t;
+    return LBM_OK;
+}
+
+int lbm_set_probes(lbm_ctx* c, const int32_t* cells, int32_t np)
+{
+    if (!c) return LBM_EINVAL;
+    if (np < 0 || np > 4096 || (np > 0 && !cells)) return fail(c, LBM_EINVAL, "bad probe list");
+    const Geo& g = c->d.g;
+    for (int p = 0; p < np; p++) {
+        const int x = cells[3 * p], y = cells[3 * p + 1], z = cells[3 * p + 2];
+        if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz)
+            return fail(c, LBM_EINVAL, "probe cell outside the grid");
+    }
+    if (c->probes) {
+        HIPCHK(c, hipStreamSynchronize(c->stream), "probe sync");
+        (void)hipFree(c->probes);
+        c->probes = nullptr;
+    }
+    c->np = 0;
+    if (np == 0) return LBM_OK;
+    int rc = device_alloc(c, (void**)&c->probes, (size_t)np * 3 * sizeof(int), "probes");
+    if (rc != LBM_OK) return rc;
+    HIPCHK(c, hipMemcpy(c->probes, cells, (size_t)np * 3 * sizeof(int), hipMemcpyHostToDevice), "probe upload");
+    c->np = np;
+    return LBM_OK;
+}
+
+int lbm_probe_accumulate(lbm_ctx* c, void* acc)
+{
+    if (!c) return LBM_EINVAL;
+    if (!acc) return fail(c, LBM_EINVAL, "NULL accumulator");
+    if (c->np == 0) return fail(c, LBM_ESTATE, "no probes registered");
+    HIPCHK(c, launch_probe_cells(c->d, c->phase, c->probes, c->np, acc, c->stream), "probe accumulate");
+    return LBM_OK;
+}
+
+int lbm_set_stats(lbm_ctx* c, void* acc, int32_t stride)
+{
+    if (!c) return LBM_EINVAL;
+    if (!acc || stride <= 0) {
+        c->stats = nullptr;
+        c->stats_stride = 0;
+        return LBM_OK;
+    }
+    c->stats = acc;
+    c->stats_stride = stride;
+    return LBM_OK;
+}
+
+int lbm_push_step(lbm_ctx* c, const void* src, void* dst)
+{
+    if (!c) return LBM_EINVAL;
+    if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct device arrays");
+    int rc = check_ready(c);
+    if (rc != LBM_OK) return rc;
+    HIPCHK(c, launch_push(c->d, src, dst, c->stream), "push step");
+    return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* lam, const void* probe_src,
+                     void* g_inflow)
+{
+    if (!c) return LBM_EINVAL;
+    if (!f_t || !lam_next || !lam || lam == lam_next) return fail(c, LBM_EINVAL, "bad adjoint arguments");
+    if (probe_src && c->np == 0) return fail(c, LBM_ESTATE, "probe source without registered probes");
+    int rc = check_ready(c);
+    if (rc != LBM_OK) return rc;
+    HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, c->probes, c->np, probe_src, g_inflow, c->stream),
+           "adjoint step");
+    return LBM_OK;
+}
+
+int lbm_profile(lbm_ctx* c, int32_t enable)
+{
+    if (!c) return LBM_EINVAL;
+    c->profiling = enable != 0;
+    c->ev_used = 0;
+    return LBM_OK;
+}
+
+int lbm_profile_read(lbm_ctx* c, double* total_ms, int64_t* launches)
+{
+    if (!c) return LBM_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "profile sync");
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]), "event elapsed");
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)(c->ev_used / 2);
+    c->ev_used = 0;
+    return LBM_OK;
+}
+
+}  // extern "C"
