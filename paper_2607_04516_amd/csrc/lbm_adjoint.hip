@@ -1,12 +1,363 @@
-// Discrete adjoint of the D3Q19 LBM-LES step (not yet built: reports an error).
+// Discrete adjoint of the D3Q19 LBM-LES step for gfx950.
+//
+// The forward step is f(t+1) = S(C(f(t)), u_in): C the local collision of
+// App. D (eqs. D.1-D.4, D.8, D.10, D.11, Guo source), S the streaming with
+// its boundary rules, inflow cells supplying feq(rho0, u_in).  One adjoint
+// step computes
+//   lam(t) = J_C(f(t))^T S^T lam(t+1)            (+ probe sources)
+//   g[face][z] += sum over the face's inflow cells of lam*_k d feq_k/du_in
+// on canonical unpadded arrays:
+//   * S^T is a gather: the post-collision population k of cell x lands in
+//     the slot that the pull of direction opp(k) at x resolves to (the same
+//     slot the forward scatter writes), plus every zero-gradient outflow
+//     copy of that slot (up to 7 at an outflow corner);
+//   * J_C^T is applied matrix-free from the hand-derived derivatives of the
+//     moments, the equilibrium, the invariant Q and tau_eff.
+// Solid and inflow cells get lam = 0 (their state is not a variable).
+#include "lbm_device.h"
 #include "lbm_launch.h"
+
+#include <type_traits>
 
 namespace lbm {
 
-hipError_t launch_adjoint(const DevCtx&, const void*, const void*, void*, const int*, int, const void*, void*,
-                          hipStream_t)
+template <int I, int N, class Fn>
+__device__ __forceinline__ void adj_static_for(Fn&& fn)
 {
-    return hipErrorNotSupported;
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        adj_static_for<I + 1, N>(fn);
+    }
+}
+
+__device__ inline long long cidx(const Geo& g, int x, int y, int z)
+{
+    return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+// Sum of lam_next over the zero-gradient outflow copies of slot (d, m):
+// every outflow cell c whose entering population m copies what d receives.
+template <typename R>
+__device__ inline R copy_partner_sum(const R* lam_next, const uint64_t* __restrict__ mask, const Geo& g, int dx,
+                                     int dy, int dz, int m, int vx, int vy, int vz)
+{
+    int ax[3], sg[3], ne = 0;
+    const int d[3] = {dx, dy, dz};
+    const int v[3] = {vx, vy, vz};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int n = dimn(g, a);
+        if (v[a] == -1 && g.face[2 * a + 1] == F_OUTFLOW && d[a] == n - 2) { ax[ne] = a; sg[ne] = 1; ne++; }
+        if (v[a] == 1 && g.face[2 * a] == F_OUTFLOW && d[a] == 1) { ax[ne] = a; sg[ne] = -1; ne++; }
+    }
+    R s = R(0);
+    if (ne == 0) return s;
+    for (int sub = 1; sub < (1 << ne); sub++) {
+        int c[3] = {dx, dy, dz};
+        for (int k = 0; k < ne; k++)
+            if ((sub >> k) & 1) c[ax[k]] += sg[k];
+        if (!solid_at(mask, g, c[0], c[1], c[2]) && inflow_face_of(g, c[0], c[1], c[2]) < 0)
+            s += lam_next[(long long)m * g.N + cidx(g, c[0], c[1], c[2])];
+    }
+    return s;
+}
+
+// lam* of post-collision population opp(I) of cell (x,y,z): lam_next at
+// every slot that value is streamed into.  INFLOW: the cell is an inflow
+// cell (its forward scatter has no outflow rule and its own slots are void).
+template <typename R, int I, bool INFLOW>
+__device__ inline R adj_gather(const R* lam_next, const uint64_t* __restrict__ mask, const Geo& g, int x, int y, int z)
+{
+    if constexpr (!INFLOW) {
+        int qx, qy, qz, owner;
+        if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
+            // opp(I) leaves through an outflow face: only the bounce-back of a
+            // solid inner neighbour keeps it, in the cell's own slot I
+            if (!solid_at(mask, g, qx, qy, qz)) return R(0);
+            constexpr V3 c = dirv(I);
+            return lam_next[(long long)I * g.N + cidx(g, x, y, z)] +
+                   copy_partner_sum<R>(lam_next, mask, g, x, y, z, I, c.x, c.y, c.z);
+        }
+    }
+    const Res r = resolve_plain<I>(g, mask, x, y, z);
+    if (r.kind != 0) return R(0);
+    if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return R(0);
+    if constexpr (INFLOW) {
+        if (r.x == x && r.y == y && r.z == z) return R(0);
+    }
+    return lam_next[(long long)r.dir * g.N + cidx(g, r.x, r.y, r.z)] +
+           copy_partner_sum<R>(lam_next, mask, g, r.x, r.y, r.z, r.dir, r.vx, r.vy, r.vz);
+}
+
+// mu = J_C(h)^T ls for one cell (h shifted populations, in place into ls).
+template <typename R>
+__device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
+{
+    R drho, ux, uy, uz, inv_rho;
+    moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+    const R rho = P.rho0 + drho;
+    R heq[NQ];
+    equilibrium_shifted<R>(rho, drho, ux, uy, uz, heq);
+    // non-equilibrium flux and closure
+    R neq[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; i++) neq[i] = h[i] - heq[i];
+    R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < NQ; i++) {
+        const V3 c = dirv(i);
+        pxx += R(c.x * c.x) * neq[i];
+        pyy += R(c.y * c.y) * neq[i];
+        pzz += R(c.z * c.z) * neq[i];
+        pxy += R(c.x * c.y) * neq[i];
+        pxz += R(c.x * c.z) * neq[i];
+        pyz += R(c.y * c.z) * neq[i];
+    }
+    const R pp = (pxx * pxx + pyy * pyy + pzz * pzz) + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+    const R q = sqrt(R(2) * pp);
+    const R D = P.tau0 * P.tau0 + P.ksmag * q * inv_rho;
+    const R sD = sqrt(D);
+    const R tau = R(0.5) * (P.tau0 + sD);
+    const R omega = R(1) / tau;
+
+    // reductions over lam*
+    R A = 0, G = 0, Pw = 0;              // sum ls feq/rho, sum ls neq, sum ls w B
+    R s0 = 0, sx = 0, sy = 0, sz = 0;    // sum w ls, sum w ls c
+    R tx = 0, ty = 0, tz = 0;            // sum w ls (c.u) c
+    R ex = 0, ey = 0, ez = 0;            // sum w ls c (c.F)
+#pragma unroll
+    for (int i = 0; i < NQ; i++) {
+        const V3 c = dirv(i);
+        const R w = weight<R>(i);
+        const R l = ls[i];
+        const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
+        A += l * (heq[i] + w * P.rho0);
+        G += l * neq[i];
+        const R wl = w * l;
+        s0 += wl;
+        sx += R(c.x) * wl;
+        sy += R(c.y) * wl;
+        sz += R(c.z) * wl;
+        tx += R(c.x) * e * wl;
+        ty += R(c.y) * e * wl;
+        tz += R(c.z) * e * wl;
+        if (P.has_force) {
+            const R cF = R(c.x) * P.F[0] + R(c.y) * P.F[1] + R(c.z) * P.F[2];
+            const R uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+            Pw += wl * (R(3) * (cF - uF) + R(9) * e * cF);
+            ex += R(c.x) * cF * wl;
+            ey += R(c.y) * cF * wl;
+            ez += R(c.z) * cF * wl;
+        }
+    }
+    A *= inv_rho;
+    // V_a = rho (3 sum w l c_a + 9 sum w l e c_a - 3 u_a sum w l);  E_a = -3 F_a sum w l + 9 sum w l c_a (c.F)
+    const R vx = rho * (R(3) * sx + R(9) * tx - R(3) * ux * s0);
+    const R vy = rho * (R(3) * sy + R(9) * ty - R(3) * uy * s0);
+    const R vz = rho * (R(3) * sz + R(9) * tz - R(3) * uz * s0);
+    R Wx = omega * vx, Wy = omega * vy, Wz = omega * vz;
+    if (P.has_force) {
+        const R pre = R(1) - R(0.5) * omega;
+        Wx += pre * (R(-3) * P.F[0] * s0 + R(9) * ex);
+        Wy += pre * (R(-3) * P.F[1] * s0 + R(9) * ey);
+        Wz += pre * (R(-3) * P.F[2] * s0 + R(9) * ez);
+    }
+    Wx *= inv_rho;
+    Wy *= inv_rho;
+    Wz *= inv_rho;
+    const R Wu = Wx * ux + Wy * uy + Wz * uz;
+    // closure: -(d omega/d f_j)(G + P/2) = Z (dQ_j - Q/rho)
+    R Z = R(0), twoq = R(0), base = R(0);
+    R pux = 0, puy = 0, puz = 0;
+    if (P.ksmag > R(0) && q > R(0)) {
+        Z = (G + R(0.5) * Pw) * omega * omega * P.ksmag / (R(4) * sD) * inv_rho;
+        twoq = R(2) / q;
+        pux = pxx * ux + pxy * uy + pxz * uz;
+        puy = pxy * ux + pyy * uy + pyz * uz;
+        puz = pxz * ux + pyz * uy + pzz * uz;
+        const R upu = ux * pux + uy * puy + uz * puz;
+        base = upu - (pxx + pyy + pzz) / R(3);   // dQ_j = (2/Q)[c.Pi.c - 2 c.Pi u + base]
+    }
+    const R Zq = Z * q * inv_rho;
+    const R omA = omega * A;
+    const R om1 = R(1) - omega;
+#pragma unroll
+    for (int j = 0; j < NQ; j++) {
+        const V3 c = dirv(j);
+        R mu = om1 * ls[j] + omA + (R(c.x) * Wx + R(c.y) * Wy + R(c.z) * Wz) - Wu;
+        if (P.ksmag > R(0)) {
+            const R cpc = R(c.x * c.x) * pxx + R(c.y * c.y) * pyy + R(c.z * c.z) * pzz +
+                          R(2) * (R(c.x * c.y) * pxy + R(c.x * c.z) * pxz + R(c.y * c.z) * pyz);
+            const R cpu = R(c.x) * pux + R(c.y) * puy + R(c.z) * puz;
+            const R dq = twoq * (cpc - R(2) * cpu + base);
+            mu += Z * dq - Zq;
+        }
+        ls[j] = mu;
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
+          typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask, Geo g,
+          Phys<typename Codec<K>::real> P)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const int x = (int)(n % g.nx);
+    const long long row = n / g.nx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) {
+#pragma unroll
+        for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] = R(0);
+        return;
+    }
+    R ls[NQ], h[NQ];
+    adj_static_for<0, NQ>([&](auto ic) {
+        constexpr int k = decltype(ic)::value;
+        ls[k] = adj_gather<R, opp(k), false>(lam_next, mask, g, x, y, z);
+    });
+#pragma unroll
+    for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
+    collision_transpose<R>(h, ls, P);
+#pragma unroll
+    for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] = ls[j];
+}
+
+// dL/du_in(face F, height z): one block per z, a fixed-order tree over the
+// face's inflow cells at that height, then a compensated (Neumaier) update
+// of g[0] (sum) and g[1] (compensation).
+constexpr int ADJ_RED = 256;
+
+template <int K>
+__global__ void __launch_bounds__(ADJ_RED)
+k_adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next, const uint64_t* __restrict__ mask,
+                 const double* __restrict__ prof, Geo g, Phys<typename Codec<K>::real> P, int F,
+                 typename Codec<K>::real* gacc)
+{
+    using R = typename Codec<K>::real;
+    const int zz = blockIdx.x;
+    const int a = F >> 1;
+    // cells of face F at height zz
+    long long count;
+    if (a == 0) count = g.ny;
+    else if (a == 1) count = g.nx;
+    else count = ((F & 1) ? g.nz - 1 : 0) == zz ? (long long)g.nx * g.ny : 0;
+    R acc[3] = {R(0), R(0), R(0)};
+    R ux, uy, uz;
+    {
+        const double* p = prof + ((long long)F * g.nz + zz) * 3;
+        ux = R(p[0]);
+        uy = R(p[1]);
+        uz = R(p[2]);
+    }
+    for (long long t = threadIdx.x; t < count; t += ADJ_RED) {
+        int x, y, z = zz;
+        if (a == 0) { x = (F & 1) ? g.nx - 1 : 0; y = (int)t; }
+        else if (a == 1) { y = (F & 1) ? g.ny - 1 : 0; x = (int)t; }
+        else { x = (int)(t % g.nx); y = (int)(t / g.nx); }
+        if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) != F) continue;
+        adj_static_for<0, NQ>([&](auto ic) {
+            constexpr int k = decltype(ic)::value;
+            constexpr V3 c = dirv(k);
+            const R l = adj_gather<R, opp(k), true>(lam_next, mask, g, x, y, z);
+            const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
+            const R wl = weight<R>(k) * P.rho0 * l;
+            acc[0] += wl * (R(3) * R(c.x) + R(9) * e * R(c.x) - R(3) * ux);
+            acc[1] += wl * (R(3) * R(c.y) + R(9) * e * R(c.y) - R(3) * uy);
+            acc[2] += wl * (R(3) * R(c.z) + R(9) * e * R(c.z) - R(3) * uz);
+        });
+    }
+    __shared__ R sh[3][ADJ_RED];
+    for (int k = 0; k < 3; k++) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = ADJ_RED / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 3; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3 && count > 0) {
+        const long long o = ((long long)F * g.nz + zz) * 3 + threadIdx.x;
+        const long long o2 = 6ll * g.nz * 3 + o;
+        const R xv = sh[threadIdx.x][0];
+        const R s = gacc[o];
+        const R tsum = s + xv;
+        R comp = gacc[o2];
+        if (fabs((double)s) >= fabs((double)xv)) comp += (s - tsum) + xv;
+        else comp += (xv - tsum) + s;
+        gacc[o] = tsum;
+        gacc[o2] = comp;
+    }
+}
+
+// Probe sources: lam(x_p) += src_p . (c_j - u)/rho, probes in order (one
+// thread, so repeated cells add deterministically).
+template <int K>
+__global__ void k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_t, typename Codec<K>::real* lam,
+                                 const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P,
+                                 const int* probes, int np, const typename Codec<K>::real* src)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int p = 0; p < np; p++) {
+        const int x = probes[3 * p], y = probes[3 * p + 1], z = probes[3 * p + 2];
+        if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) continue;
+        const long long n = cidx(g, x, y, z);
+        R h[NQ];
+        for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
+        R drho, ux, uy, uz, inv_rho;
+        moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+        const R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
+        const R su = sx * ux + sy * uy + sz * uz;
+        for (int j = 0; j < NQ; j++) {
+            const V3 c = dirv(j);
+            lam[(long long)j * g.N + n] += (R(c.x) * sx + R(c.y) * sy + R(c.z) * sz - su) * inv_rho;
+        }
+    }
+}
+
+template <int K>
+static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
+                            int np, const void* probe_src, void* g_inflow, hipStream_t s)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    Phys<R> P;
+    P.tau0 = R(d.tau0);
+    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
+    P.rho0 = R(d.rho0);
+    for (int a = 0; a < 3; a++) P.F[a] = R(d.force[a]);
+    P.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+    const Geo& g = d.g;
+    if (g_inflow) {
+        // the inflow gradient reads lam_next before lam is written (lam != lam_next)
+        for (int F = 0; F < 6; F++) {
+            if (g.face[F] != F_INFLOW) continue;
+            hipLaunchKernelGGL((k_adjoint_inflow<K>), dim3(g.nz), dim3(ADJ_RED), 0, s, (const R*)lam_next, d.mask,
+                               d.prof, g, P, F, (R*)g_inflow);
+        }
+    }
+    hipLaunchKernelGGL((k_adjoint<K>), dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, s,
+                       (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P);
+    if (probe_src && np > 0)
+        hipLaunchKernelGGL((k_adjoint_probes<K>), dim3(1), dim3(64), 0, s, (const typename C::store*)f_t, (R*)lam,
+                           d.mask, g, P, probes, np, (const R*)probe_src);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
+                          int np, const void* probe_src, void* g_inflow, hipStream_t s)
+{
+    switch (d.codec) {
+        case 0: return adjoint_k<0>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
+        case 1: return adjoint_k<1>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
+        case 2: return adjoint_k<2>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
+        case 3: return adjoint_k<3>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace lbm

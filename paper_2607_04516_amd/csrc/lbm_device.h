@@ -190,6 +190,7 @@ struct Res {
     int kind;
     int x, y, z;
     int dir;
+    int vx, vy, vz;  // velocity of direction dir
 };
 
 template <int I>
@@ -202,6 +203,7 @@ __device__ inline Res resolve_plain(const Geo& g, const uint64_t* __restrict__ m
     Res r;
     r.kind = 0;
     r.x = x; r.y = y; r.z = z; r.dir = I;  // valid in-bounds slot even when kind == 2
+    r.vx = c.x; r.vy = c.y; r.vz = c.z;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const int ca = comp(c, a);
@@ -211,7 +213,6 @@ __device__ inline Res resolve_plain(const Geo& g, const uint64_t* __restrict__ m
         if (!(lo || hi)) continue;
         const int kind = g.face[lo ? 2 * a : 2 * a + 1];
         if (kind == F_WALL) {
-            r.x = x; r.y = y; r.z = z; r.dir = I;
             return r;
         } else if (kind == F_PERIODIC) {
             s[a] = lo ? s[a] + n : s[a] - n;
@@ -223,10 +224,7 @@ __device__ inline Res resolve_plain(const Geo& g, const uint64_t* __restrict__ m
             return r;
         }
     }
-    if (solid_at(mask, g, s[0], s[1], s[2])) {
-        r.x = x; r.y = y; r.z = z; r.dir = I;
-        return r;
-    }
+    if (solid_at(mask, g, s[0], s[1], s[2])) return r;
     // j = I with the mirrored components flipped; the value sits in slot opp(j)
     constexpr int o0 = opp(mirrored(I, 0)), o1 = opp(mirrored(I, 1)), o2 = opp(mirrored(I, 2)),
                   o3 = opp(mirrored(I, 3)), o4 = opp(mirrored(I, 4)), o5 = opp(mirrored(I, 5)),
@@ -243,6 +241,10 @@ __device__ inline Res resolve_plain(const Geo& g, const uint64_t* __restrict__ m
         default: d = o7; break;
     }
     r.x = s[0]; r.y = s[1]; r.z = s[2]; r.dir = d;
+    // slot opp(j): velocity -c_j, j = I with the mirrored components negated
+    r.vx = (m & 1) ? c.x : -c.x;
+    r.vy = (m & 2) ? c.y : -c.y;
+    r.vz = (m & 4) ? c.z : -c.z;
     return r;
 }
 
@@ -289,8 +291,10 @@ __device__ inline Res resolve_full(const Geo& g, const uint64_t* __restrict__ ma
     int qx, qy, qz, owner;
     if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
         if (solid_at(mask, g, qx, qy, qz)) {
+            constexpr V3 c = dirv(I);
             Res r;
             r.kind = 0; r.x = x; r.y = y; r.z = z; r.dir = I;
+            r.vx = c.x; r.vy = c.y; r.vz = c.z;
             return r;
         }
         return resolve_plain<I>(g, mask, qx, qy, qz);
