@@ -71,6 +71,55 @@ def time_forward(w, storage, steps, warmup):
             "mass": m, "energy": e}
 
 
+def time_adjoint(steps=1000, every=50):
+    """Adjoint workload: 256 x 256 x 96 urban grid, FP32, T steps with a
+    checkpoint every K; loss = sum over 24 probes of |u_bar - target|^2,
+    gradient with respect to 96 inflow speeds and the angle.  Returns the
+    plain-forward, checkpointed-forward and backward times."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2607_04516_amd import adjoint, binding, workloads
+    w = workloads.adjoint_urban("f32", steps)
+    lat = binding.from_workload(w)
+    base = workloads.power_law_speeds(w.nz, 0.08, 100.0, 0.25)
+    prob = adjoint.InflowProblem(lat, w.probes, steps, every, w.u0)
+    rng = np.random.default_rng(12)
+    tgt, _ = prob.run_forward(base * (1 + 0.05 * rng.uniform(-1, 1, base.shape)), math.radians(5.0),
+                              keep_checkpoints=False)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    # plain forward: T steps, nothing else
+    lat.reset(w.u0)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    lat.step(steps)
+    b.record()
+    torch.cuda.synchronize()
+    t_plain = a.elapsed_time(b)
+    sp = torch.tensor(base, dtype=torch.float64, requires_grad=True)
+    th = torch.tensor(0.0, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = adjoint.probe_misfit(prob, sp, th, tgt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fluid, _ = lat.cell_counts()
+    g = np.concatenate([sp.grad.numpy(), [float(th.grad)]])
+    lat.close()
+    return {"workload": f"{w.name}, FP32, T={steps}, K={every}, {len(w.probes)} probes, 97 parameters",
+            "forward_plain_ms": round(t_plain, 2), "forward_ckpt_ms": round((t1 - t0) * 1e3, 2),
+            "backward_ms": round((t2 - t1) * 1e3, 2),
+            "cost_ratio": round(((t1 - t0) + (t2 - t1)) * 1e3 / t_plain, 3),
+            "adjoint_mlups": round(fluid * steps / (t2 - t1) / 1e6, 1),
+            "loss": float(L), "grad_norm": float(np.linalg.norm(g))}
+
+
 def cpu_baseline(w, seconds=12.0, crop=(160, 160)):
     """The FP64 oracle (single thread) on a crop of the workload: the first
     crop[0] x crop[1] columns with the full height, same faces and profiles."""
@@ -108,6 +157,7 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage runs")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost run")
     ap.add_argument("--nx", type=int, default=800)
     ap.add_argument("--ny", type=int, default=800)
     ap.add_argument("--nz", type=int, default=128)
@@ -141,6 +191,12 @@ def main():
             print(f"[bench] {s}: {r['mlups']:.0f} MLUPS, {r['achieved_gbs']:.0f} GB/s", file=sys.stderr,
                   flush=True)
 
+    adj = None
+    if not args.no_adjoint:
+        print("[bench] adjoint workload", file=sys.stderr, flush=True)
+        adj = time_adjoint()
+        print(f"[bench] adjoint: {adj}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a crop", file=sys.stderr, flush=True)
@@ -172,6 +228,8 @@ def main():
     }
     if extra:
         line["storage_forms"] = extra
+    if adj:
+        line["adjoint"] = adj
     print(json.dumps(line), flush=True)
 
 

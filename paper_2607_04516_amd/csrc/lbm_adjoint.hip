@@ -41,23 +41,25 @@ template <typename R>
 __device__ inline R copy_partner_sum(const R* lam_next, const uint64_t* __restrict__ mask, const Geo& g, int dx,
                                      int dy, int dz, int m, int vx, int vy, int vz)
 {
-    int ax[3], sg[3], ne = 0;
-    const int d[3] = {dx, dy, dz};
-    const int v[3] = {vx, vy, vz};
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const int n = dimn(g, a);
-        if (v[a] == -1 && g.face[2 * a + 1] == F_OUTFLOW && d[a] == n - 2) { ax[ne] = a; sg[ne] = 1; ne++; }
-        if (v[a] == 1 && g.face[2 * a] == F_OUTFLOW && d[a] == 1) { ax[ne] = a; sg[ne] = -1; ne++; }
-    }
+    // per axis: the side (+1 high, -1 low) of an outflow face that m enters
+    // and d lies next to, or 0
+    int sx = 0, sy = 0, sz = 0;
+    if (vx == -1 && g.face[1] == F_OUTFLOW && dx == g.nx - 2) sx = 1;
+    else if (vx == 1 && g.face[0] == F_OUTFLOW && dx == 1) sx = -1;
+    if (vy == -1 && g.face[3] == F_OUTFLOW && dy == g.ny - 2) sy = 1;
+    else if (vy == 1 && g.face[2] == F_OUTFLOW && dy == 1) sy = -1;
+    if (vz == -1 && g.face[5] == F_OUTFLOW && dz == g.nz - 2) sz = 1;
+    else if (vz == 1 && g.face[4] == F_OUTFLOW && dz == 1) sz = -1;
     R s = R(0);
-    if (ne == 0) return s;
-    for (int sub = 1; sub < (1 << ne); sub++) {
-        int c[3] = {dx, dy, dz};
-        for (int k = 0; k < ne; k++)
-            if ((sub >> k) & 1) c[ax[k]] += sg[k];
-        if (!solid_at(mask, g, c[0], c[1], c[2]) && inflow_face_of(g, c[0], c[1], c[2]) < 0)
-            s += lam_next[(long long)m * g.N + cidx(g, c[0], c[1], c[2])];
+    if ((sx | sy | sz) == 0) return s;
+    // every non-empty subset of those axes moves d onto one copy cell
+    for (int sub = 1; sub < 8; sub++) {
+        if (((sub & 1) && !sx) || ((sub & 2) && !sy) || ((sub & 4) && !sz)) continue;
+        const int cx = dx + ((sub & 1) ? sx : 0);
+        const int cy = dy + ((sub & 2) ? sy : 0);
+        const int cz = dz + ((sub & 4) ? sz : 0);
+        if (!solid_at(mask, g, cx, cy, cz) && inflow_face_of(g, cx, cy, cz) < 0)
+            s += lam_next[(long long)m * g.N + cidx(g, cx, cy, cz)];
     }
     return s;
 }
@@ -73,10 +75,9 @@ __device__ inline R adj_gather(const R* lam_next, const uint64_t* __restrict__ m
         if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
             // opp(I) leaves through an outflow face: only the bounce-back of a
             // solid inner neighbour keeps it, in the cell's own slot I
+            // (x, I) is itself an outflow copy slot: nothing copies from it
             if (!solid_at(mask, g, qx, qy, qz)) return R(0);
-            constexpr V3 c = dirv(I);
-            return lam_next[(long long)I * g.N + cidx(g, x, y, z)] +
-                   copy_partner_sum<R>(lam_next, mask, g, x, y, z, I, c.x, c.y, c.z);
+            return lam_next[(long long)I * g.N + cidx(g, x, y, z)];
         }
     }
     const Res r = resolve_plain<I>(g, mask, x, y, z);

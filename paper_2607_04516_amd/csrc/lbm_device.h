@@ -76,35 +76,46 @@ enum { F_PERIODIC = 0, F_INFLOW = 1, F_OUTFLOW = 2, F_FREESLIP = 3, F_WALL = 4 }
 template <int K>
 struct Codec;
 
+// dec/enc convert to and from the true shift h; raw/pack convert without
+// the scale (the step kernels work in stored units, SC times h).
 template <>
 struct Codec<0> {  // FP64
     using store = double;
     using real = double;
+    static constexpr int SC = 1;
     __device__ static real dec(store v) { return v; }
     __device__ static store enc(real v) { return v; }
+    __device__ static real raw(store v) { return v; }
+    __device__ static store pack(real v) { return v; }
 };
 
 template <>
 struct Codec<1> {  // FP32
     using store = float;
     using real = float;
+    static constexpr int SC = 1;
     __device__ static real dec(store v) { return v; }
     __device__ static store enc(real v) { return v; }
+    __device__ static real raw(store v) { return v; }
+    __device__ static store pack(real v) { return v; }
 };
 
 template <>
 struct Codec<2> {  // IEEE binary16, round to nearest even, scaled by 2^8
     using store = _Float16;
     using real = float;
-    static constexpr float scale = 256.0f;
-    __device__ static real dec(store v) { return float(v) * (1.0f / scale); }
-    __device__ static store enc(real v) { return store(v * scale); }
+    static constexpr int SC = 256;
+    __device__ static real dec(store v) { return float(v) * (1.0f / SC); }
+    __device__ static store enc(real v) { return store(v * float(SC)); }
+    __device__ static real raw(store v) { return float(v); }
+    __device__ static store pack(real v) { return store(v); }
 };
 
 template <>
 struct Codec<3> {  // bfloat16, round to nearest even
     using store = uint16_t;
     using real = float;
+    static constexpr int SC = 1;
     __device__ static real dec(store v) { return __uint_as_float(uint32_t(v) << 16); }
     __device__ static store enc(real v)
     {
@@ -112,6 +123,8 @@ struct Codec<3> {  // bfloat16, round to nearest even
         u += 0x7FFFu + ((u >> 16) & 1u);
         return store(u >> 16);
     }
+    __device__ static real raw(store v) { return dec(v); }
+    __device__ static store pack(real v) { return enc(v); }
 };
 
 // --------------------------------------------------------------------------
@@ -399,6 +412,141 @@ __device__ inline void collide(R* h, const Phys<R>& P, R& drho_out, R& ux, R& uy
     }
     drho_out = drho;
     tau_out = tau;
+}
+
+// Fast reciprocal and square root: hardware v_rcp_f32 / v_sqrt_f32 (about
+// 1 ulp) for float; correctly rounded for double.
+template <typename R>
+__device__ inline R fast_rcp(R x) { return R(1) / x; }
+template <>
+__device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename R>
+__device__ inline R fast_sqrt(R x) { return sqrt(x); }
+template <>
+__device__ inline float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// --------------------------------------------------------------------------
+// The collision of one cell in the form the step kernels use.  h holds the
+// stored shifts (SC times f_i - w_i rho0); the update is the same BGK +
+// Smagorinsky step as collide() with fewer operations:
+//   * opposite pairs enter through s_k = h_i + h_j and d_k = h_i - h_j;
+//   * Pi comes from the raw second moment of h and the exact D3Q19
+//     identity sum_i c_ia c_ib feq_i = rho (delta_ab/3 + u_a u_b)
+//     (4th-order isotropy, App. D), so no per-direction feq is formed;
+//   * h*_i = (1 - w) h_i + w heq_i is evaluated per pair from the even and
+//     odd parts of heq.
+// Returns rho - rho0, u and tau_eff.
+// --------------------------------------------------------------------------
+// rho - rho0 and u of stored shifts h (SC times the true shifts), in the
+// summation order of collide_pairs, so diagnostics match the collision bit
+// for bit.
+template <typename R, int SC>
+__device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz)
+{
+    constexpr R isc = R(1) / R(SC);
+    const R s1 = h[1] + h[2], d1 = h[1] - h[2];
+    const R s2 = h[3] + h[4], d2 = h[3] - h[4];
+    const R s3 = h[5] + h[6], d3 = h[5] - h[6];
+    const R s4 = h[7] + h[8], d4 = h[7] - h[8];
+    const R s5 = h[9] + h[10], d5 = h[9] - h[10];
+    const R s6 = h[11] + h[12], d6 = h[11] - h[12];
+    const R s7 = h[13] + h[14], d7 = h[13] - h[14];
+    const R s8 = h[15] + h[16], d8 = h[15] - h[16];
+    const R s9 = h[17] + h[18], d9 = h[17] - h[18];
+    const R drs = ((h[0] + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)) + (s8 + s9);
+    const R jx = ((d1 + d4) + (d5 + d7)) + d8;
+    const R jy = ((d2 + d4) + (d6 - d7)) + d9;
+    const R jz = ((d3 + d5) + (d6 - d8)) - d9;
+    drho = drs * isc;
+    const R irho = fast_rcp<R>(P.rho0 + drho);
+    ux = (jx * isc + R(0.5) * P.F[0]) * irho;
+    uy = (jy * isc + R(0.5) * P.F[1]) * irho;
+    uz = (jz * isc + R(0.5) * P.F[2]) * irho;
+}
+
+template <typename R, int SC>
+__device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R& uy, R& uz, R& tau_o)
+{
+    constexpr R isc = R(1) / R(SC);
+    const R s1 = h[1] + h[2], d1 = h[1] - h[2];
+    const R s2 = h[3] + h[4], d2 = h[3] - h[4];
+    const R s3 = h[5] + h[6], d3 = h[5] - h[6];
+    const R s4 = h[7] + h[8], d4 = h[7] - h[8];
+    const R s5 = h[9] + h[10], d5 = h[9] - h[10];
+    const R s6 = h[11] + h[12], d6 = h[11] - h[12];
+    const R s7 = h[13] + h[14], d7 = h[13] - h[14];
+    const R s8 = h[15] + h[16], d8 = h[15] - h[16];
+    const R s9 = h[17] + h[18], d9 = h[17] - h[18];
+    const R drs = ((h[0] + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)) + (s8 + s9);
+    const R jx = ((d1 + d4) + (d5 + d7)) + d8;
+    const R jy = ((d2 + d4) + (d6 - d7)) + d9;
+    const R jz = ((d3 + d5) + (d6 - d8)) - d9;
+    const R mxx = ((s1 + s4) + (s5 + s7)) + s8;
+    const R myy = ((s2 + s4) + (s6 + s7)) + s9;
+    const R mzz = ((s3 + s5) + (s6 + s8)) + s9;
+    const R mxy = s4 - s7, mxz = s5 - s8, myz = s6 - s9;
+    const R drho = drs * isc;
+    const R rho = P.rho0 + drho;
+    const R irho = fast_rcp<R>(rho);
+    ux = (jx * isc + R(0.5) * P.F[0]) * irho;
+    uy = (jy * isc + R(0.5) * P.F[1]) * irho;
+    uz = (jz * isc + R(0.5) * P.F[2]) * irho;
+    const R t3 = drho * R(1.0 / 3.0);
+    const R rux = rho * ux, ruy = rho * uy;
+    const R pxx = (mxx * isc - t3) - rux * ux;
+    const R pyy = (myy * isc - t3) - ruy * uy;
+    const R pzz = (mzz * isc - t3) - rho * uz * uz;
+    const R pxy = mxy * isc - rux * uy;
+    const R pxz = mxz * isc - rux * uz;
+    const R pyz = myz * isc - ruy * uz;
+    const R pp = (pxx * pxx + pyy * pyy + pzz * pzz) + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+    const R q = fast_sqrt<R>(R(2) * pp);
+    const R tau = R(0.5) * (P.tau0 + fast_sqrt<R>(P.tau0 * P.tau0 + P.ksmag * q * irho));
+    const R om = fast_rcp<R>(tau);
+    const R om1 = R(1) - om;
+    // heq_i = w_i [drho - 1.5 rho u.u] + w_i rho (4.5 e^2 +- 3 e), times SC
+    const R base = drho - R(1.5) * rho * (ux * ux + uy * uy + uz * uz);
+    const R a0 = om * R(SC) * weight<R>(0), af = om * R(SC) * weight<R>(1), ae = om * R(SC) * weight<R>(7);
+    const R c0 = a0 * base, cf = af * base, ce = ae * base;
+    const R bf = af * R(4.5) * rho, be = ae * R(4.5) * rho;
+    const R gf = af * R(3) * rho, ge = ae * R(3) * rho;
+    h[0] = om1 * h[0] + c0;
+#define LBM_PAIR(i, e, C, B, G)                 \
+    {                                           \
+        const R ee = (e);                       \
+        const R t = (B) * (ee * ee) + (C);      \
+        const R o = (G) * ee;                   \
+        h[i] = om1 * h[i] + (t + o);            \
+        h[i + 1] = om1 * h[i + 1] + (t - o);    \
+    }
+    LBM_PAIR(1, ux, cf, bf, gf)
+    LBM_PAIR(3, uy, cf, bf, gf)
+    LBM_PAIR(5, uz, cf, bf, gf)
+    LBM_PAIR(7, ux + uy, ce, be, ge)
+    LBM_PAIR(9, ux + uz, ce, be, ge)
+    LBM_PAIR(11, uy + uz, ce, be, ge)
+    LBM_PAIR(13, ux - uy, ce, be, ge)
+    LBM_PAIR(15, ux - uz, ce, be, ge)
+    LBM_PAIR(17, uy - uz, ce, be, ge)
+#undef LBM_PAIR
+    if (P.has_force) {
+        // Guo source (1 - w/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F, times SC
+        const R pre = (R(1) - R(0.5) * om) * R(SC);
+        const R uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+        h[0] += pre * weight<R>(0) * (R(-3) * uF);
+#pragma unroll
+        for (int i = 1; i < NQ; i += 2) {
+            const V3 c = dirv(i);
+            const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
+            const R cF = R(c.x) * P.F[0] + R(c.y) * P.F[1] + R(c.z) * P.F[2];
+            const R ev = pre * weight<R>(i) * (R(9) * e * cF - R(3) * uF);
+            const R od = pre * weight<R>(i) * (R(3) * cF);
+            h[i] += ev + od;
+            h[i + 1] += ev - od;
+        }
+    }
+    drho_o = drho;
+    tau_o = tau;
 }
 
 // splitmix64 (Steele, Lea & Flood 2014): golden-gamma increment, then the

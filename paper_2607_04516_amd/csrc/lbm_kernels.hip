@@ -60,13 +60,15 @@ template <int K, int MODE, bool STATS>
 __global__ void __launch_bounds__(256)
 k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
        const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
-       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nblocks_padded)
+       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nblocks_padded,
+       const unsigned* __restrict__ wlist)
 {
     using C = Codec<K>;
     using R = typename C::real;
     const long long blk = xcd_block(nblocks_padded);
-    const long long wave = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    long long wave = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
+    if (wlist) wave = wlist[wave];
     const int lane = threadIdx.x & 63;
     const int cx = (int)(wave % g.ncx);
     const long long row = wave / g.ncx;
@@ -100,10 +102,10 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
                 idx = (long long)opp(I) * ls.S + ns - (c.x + (long long)ls.pitch * (c.y + (long long)g.ny * c.z));
             else
                 idx = (long long)I * ls.S + ns;
-            h[I] = C::dec(src[idx]);
+            h[I] = C::raw(src[idx]);
         });
         R drho, ux, uy, uz, tau;
-        collide<R>(h, P, drho, ux, uy, uz, tau);
+        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             constexpr V3 c = dirv(I);
@@ -112,7 +114,7 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
                 idx = (long long)I * ld.S + nd;
             else
                 idx = (long long)opp(I) * ld.S + nd - (c.x + (long long)ld.pitch * (c.y + (long long)g.ny * c.z));
-            dst[idx] = C::enc(h[opp(I)]);
+            dst[idx] = C::pack(h[opp(I)]);
         });
         if constexpr (STATS) {
             const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
@@ -146,20 +148,22 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
         // inflow cell: post-collision state is feq(rho0, u_in(z)) whatever it held
         load_profile<R>(prof, g.nz, inf, z, ux, uy, uz);
         equilibrium_shifted<R>(P.rho0, R(0), ux, uy, uz, h);
+#pragma unroll
+        for (int i = 0; i < NQ; i++) h[i] *= R(C::SC);
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             if constexpr (MODE == MODE_EVEN) {
-                dst[(long long)I * ld.S + nd] = C::enc(h[opp(I)]);
+                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
             } else if constexpr (MODE == MODE_PUSH) {
                 // canonical output of an inflow cell is its own equilibrium
-                dst[(long long)I * ld.S + nd] = C::enc(h[I]);
+                dst[(long long)I * ld.S + nd] = C::pack(h[I]);
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
-                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::enc(h[opp(I)]);
+                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
             } else {
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0)
-                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::enc(h[opp(I)]);
+                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
             }
         });
     } else {
@@ -169,35 +173,35 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
             if constexpr (MODE == MODE_ODD) {
                 int qx, qy, qz, owner;
                 if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
-                    h[I] = C::dec(ghost[ghost_index<I>(g, owner, x, y, z)]);
+                    h[I] = C::raw(ghost[ghost_index<I>(g, owner, x, y, z)]);
                 } else {
                     const Res r = resolve_plain<I>(g, mask, x, y, z);
-                    h[I] = C::dec(src[(long long)r.dir * ls.S + cell_index(ls, g.ny, r.x, r.y, r.z)]);
+                    h[I] = C::raw(src[(long long)r.dir * ls.S + cell_index(ls, g.ny, r.x, r.y, r.z)]);
                 }
             } else {
-                h[I] = C::dec(src[(long long)I * ls.S + ns]);
+                h[I] = C::raw(src[(long long)I * ls.S + ns]);
             }
         });
         R drho, tau;
-        collide<R>(h, P, drho, ux, uy, uz, tau);
+        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
         // scatter
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             if constexpr (MODE == MODE_EVEN) {
-                dst[(long long)I * ld.S + nd] = C::enc(h[opp(I)]);
+                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
             } else {
                 int qx, qy, qz, owner;
                 if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
                     // opp(I) leaves through the outflow face: kept only as the
                     // bounce-back of a solid inner neighbour
-                    if (solid_at(mask, g, qx, qy, qz)) dst[(long long)I * ld.S + nd] = C::enc(h[opp(I)]);
+                    if (solid_at(mask, g, qx, qy, qz)) dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
                 } else {
                     const Res r = resolve_plain<I>(g, mask, x, y, z);
                     if (r.kind == 0) {
                         if constexpr (MODE == MODE_PUSH) {
                             if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
                         }
-                        dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::enc(h[opp(I)]);
+                        dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
                     }
                 }
             }
@@ -409,7 +413,7 @@ k_macros(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, c
             R h[NQ];
             for (int i = 0; i < NQ; i++) h[i] = C::dec(v[i]);
             R drho, tau;
-            collide<R>(h, P, drho, ux, uy, uz, tau);
+            collide_pairs<R, 1>(h, P, drho, ux, uy, uz, tau);
             r = P.rho0 + drho;
             nt = (tau - P.tau0) / R(3);
         }
@@ -444,8 +448,8 @@ __device__ inline void cell_rho_u(const typename Codec<K>::store* f, const uint6
     load_cell<K>(f, mask, g, L, phase, x, y, z, v);
     R h[NQ];
     for (int i = 0; i < NQ; i++) h[i] = C::dec(v[i]);
-    R drho, inv_rho;
-    moments<R>(h, P, drho, out[1], out[2], out[3], inv_rho);
+    R drho;
+    moments_pairs<R, 1>(h, P, drho, out[1], out[2], out[3]);
     out[0] = P.rho0 + drho;
 }
 
@@ -528,8 +532,8 @@ k_mass_partial(const typename Codec<K>::store* f, const uint64_t* __restrict__ m
         load_cell<K>(f, mask, g, L, phase, x, y, z, v);
         R h[NQ];
         for (int i = 0; i < NQ; i++) h[i] = C::dec(v[i]);
-        R drho, ux, uy, uz, inv_rho;
-        moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+        R drho, ux, uy, uz;
+        moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
         // Neumaier summation of drho
         const R tsum = s + drho;
         if (fabs((double)s) >= fabs((double)drho)) comp += (s - tsum) + drho;
@@ -615,7 +619,24 @@ static hipError_t step_k(const DevCtx& d, const void* src, void* dst, Lay ls, La
     const long long nbp = (nb + 7) / 8 * 8;
     hipLaunchKernelGGL((k_step<K, MODE, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)dst,
                        (const typename C::store*)src, d.mask, d.prof, (const typename C::store*)d.ghost, d.g, ls, ld,
-                       phys_of<K>(d), (typename C::real*)stats, nwaves, nbp);
+                       phys_of<K>(d), (typename C::real*)stats, nwaves, nbp, (const unsigned*)nullptr);
+    return hipGetLastError();
+}
+
+// General odd-step kernel over the listed waves (rows on a y or z face, x
+// faces other than inflow at x- / outflow at x+).
+template <int K, bool ST>
+static hipError_t general_odd_k(const DevCtx& d, void* stats, hipStream_t s)
+{
+    using C = Codec<K>;
+    const long long nwaves = d.odd_list_n;
+    if (nwaves == 0) return hipSuccess;
+    const long long nb = (nwaves + 3) / 4;
+    const long long nbp = (nb + 7) / 8 * 8;
+    const Lay L{d.g.S, d.g.pitch};
+    hipLaunchKernelGGL((k_step<K, MODE_ODD, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)d.f,
+                       (const typename C::store*)d.f, d.mask, d.prof, (const typename C::store*)d.ghost, d.g, L, L,
+                       phys_of<K>(d), (typename C::real*)stats, nwaves, nbp, d.odd_list);
     return hipGetLastError();
 }
 
@@ -630,21 +651,29 @@ static hipError_t step_dispatch(const DevCtx& d, int mode, const void* src, void
     return step_k<K, MODE_PUSH, false>(d, src, dst, ls, ld, nullptr, s);
 }
 
-#define LBM_DISPATCH(codec, CALL)              \
-    switch (codec) {                           \
-        case 0: { constexpr int K = 0; CALL; } \
-        case 1: { constexpr int K = 1; CALL; } \
-        case 2: { constexpr int K = 2; CALL; } \
-        case 3: { constexpr int K = 3; CALL; } \
-        default: return hipErrorInvalidValue;  \
+#define LBM_DISPATCH(codec, ...)                      \
+    switch (codec) {                                  \
+        case 0: { constexpr int K = 0; __VA_ARGS__; } \
+        case 1: { constexpr int K = 1; __VA_ARGS__; } \
+        case 2: { constexpr int K = 2; __VA_ARGS__; } \
+        case 3: { constexpr int K = 3; __VA_ARGS__; } \
+        default: return hipErrorInvalidValue;         \
     }
 
 static Lay padded(const DevCtx& d) { return Lay{d.g.S, d.g.pitch}; }
 static Lay canonical(const DevCtx& d) { return Lay{d.g.N, d.g.nx}; }
 
-hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s)
+hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s)
 {
     LBM_DISPATCH(d.codec, return step_dispatch<K>(d, odd ? MODE_ODD : MODE_EVEN, d.f, d.f, padded(d), padded(d), stats, s));
+}
+
+hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s)
+{
+    LBM_DISPATCH(d.codec, {
+        if (stats) return general_odd_k<K, true>(d, stats, s);
+        return general_odd_k<K, false>(d, stats, s);
+    });
 }
 
 hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s)

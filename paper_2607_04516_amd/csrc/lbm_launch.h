@@ -16,10 +16,24 @@ struct DevCtx {
     const uint64_t* mask; // solid bits [nz][ny][wpr]
     void* ghost;          // outflow ghost entries
     const double* prof;   // inflow profiles [6][nz][3]
+    const unsigned* odd_list;  // waves of the odd step left to the general kernel
+    long long odd_list_n;
     double tau0, c_smag, delta, rho0, force[3];
 };
 
+// Host copy of the odd kernel's test for waves it leaves to the general
+// kernel (k_odd in lbm_step.hip applies the same test).
+inline bool odd_wave_is_general(const Geo& g, int cx, int y, int z)
+{
+    if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1) return true;
+    if (cx == 0 && g.face[0] != F_INFLOW) return true;
+    if (cx * 64 + 63 >= g.nx - 1 && g.face[1] != F_OUTFLOW) return true;
+    return false;
+}
+
 hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s);
+hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s);
+hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s);
 hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s);
 hipError_t launch_outflow_ghost(const DevCtx& d, hipStream_t s);
 hipError_t launch_outflow_copy(const DevCtx& d, void* arr, int canonical_layout, hipStream_t s);

@@ -34,6 +34,7 @@ struct lbm_ctx {
     int np = 0;
     double* red_partial = nullptr;
     double* red_out = nullptr;  // device [5]
+    unsigned* odd_list = nullptr;
     void* stats = nullptr;
     int stats_stride = 0;
     int64_t fluid = 0, interior = 0;
@@ -88,7 +89,7 @@ static void free_all(lbm_ctx* c)
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->ev_used = 0;
-    void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out};
+    void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -99,6 +100,7 @@ static void free_all(lbm_ctx* c)
     c->probes = nullptr;
     c->red_partial = nullptr;
     c->red_out = nullptr;
+    c->odd_list = nullptr;
 }
 
 static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
@@ -141,7 +143,13 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         if ((lo == LBM_PERIODIC) != (hi == LBM_PERIODIC)) return fail(nullptr, LBM_EINVAL, "periodic faces must be paired");
     }
     const long long N = (long long)grid->nx * grid->ny * grid->nz;
-    if (N > (1ll << 40)) return fail(nullptr, LBM_EINVAL, "grid too large");
+    {
+        // the step kernels address two adjacent slices with 32-bit byte offsets
+        const long long pitch = ((long long)grid->nx + 63) / 64 * 64;
+        const long long slice = pitch * grid->ny * grid->nz * (long long)codec_bytes(params->storage);
+        if (2 * slice >= (1ll << 32) || (long long)grid->ny * grid->nz * (((long long)grid->nx + 63) / 64) >= (1ll << 32))
+            return fail(nullptr, LBM_EINVAL, "grid too large for one context (a population slice must stay below 2 GiB)");
+    }
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
@@ -209,6 +217,28 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         delete c;
         return rc;
     }
+    // waves of the odd step handled by the general kernel
+    std::vector<unsigned> olist;
+    for (int z = 0; z < g.nz; z++)
+        for (int y = 0; y < g.ny; y++)
+            for (int cx = 0; cx < g.ncx; cx++)
+                if (odd_wave_is_general(g, cx, y, z))
+                    olist.push_back((unsigned)(cx + (long long)g.ncx * (y + (long long)g.ny * z)));
+    if ((rc = device_alloc(c, (void**)&c->odd_list, olist.size() * sizeof(unsigned), "wave list")) != LBM_OK) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    if (!olist.empty() &&
+        hipMemcpy(c->odd_list, olist.data(), olist.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
+        g_create_error = "upload wave list";
+        free_all(c);
+        delete c;
+        return LBM_EHIP;
+    }
+    c->d.odd_list = c->odd_list;
+    c->d.odd_list_n = (long long)olist.size();
     c->prof_host.assign(18 * (size_t)g.nz, 0.0);
     hipError_t e = hipMemcpy(c->mask, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->prof, 0, 18 * (size_t)g.nz * sizeof(double));

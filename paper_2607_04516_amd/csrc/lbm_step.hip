@@ -1,0 +1,359 @@
+// The two in-place A-A step kernels of the D3Q19 LBM-LES update on gfx950.
+//
+// Even step (natural layout -> swapped): every fluid cell reads its own 19
+// slots, collides, and writes f*_i into its own slot opp(i).  No boundary
+// rule is involved, so one kernel covers every wave.
+//
+// Odd step (swapped -> natural): the pull of direction I at cell x reads
+// the slot (x - c_I, opp(I)) (or its boundary substitute) and the push of
+// opp(I) writes back into the same slot.  This kernel takes every wave whose
+// row is not on a y or z face; the remaining waves go to the general kernel
+// through a wave list built at context creation.  Inside this kernel:
+//   * one 32-bit lane offset addresses all 19 slots: each direction has its
+//     own wave-uniform 64-bit base (slice base minus the neighbour offset);
+//   * halfway bounce-back at solid neighbours is a per-lane select between
+//     the neighbour slot and the cell's own slot, driven by 64-bit lane masks
+//     that the scalar unit builds from the bit-packed solid rows (a row word
+//     covers exactly the 64 lanes of a wave);
+//   * the inflow cell of an x- INFLOW face (lane 0 of chunk 0) writes
+//     feq(rho0, u_in), the outflow cell of an x+ OUTFLOW face reads its five
+//     entering populations from the ghost plane.
+#include "lbm_device.h"
+#include "lbm_launch.h"
+
+#include <type_traits>
+
+namespace lbm {
+
+template <int I, int N, class Fn>
+__device__ __forceinline__ void sfor(Fn&& fn)
+{
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        sfor<I + 1, N>(fn);
+    }
+}
+
+// Block order: plain.  Blocks are dealt round robin to the 8 XCDs, so each
+// region of the array is streamed by all XCDs at once; grouping consecutive
+// blocks on one XCD measured slower for this stencil (no cross-block reuse
+// to gain beyond the shared edge lines of a row).
+__device__ inline long long xcd_remap(long long nblocks_padded)
+{
+    (void)nblocks_padded;
+    return blockIdx.x;
+}
+
+// Population traffic of the step kernels (plain loads and stores: the
+// streaming hint measured slower on gfx950 for this access pattern).
+template <typename T>
+__device__ inline T ld_pop(const T* p)
+{
+    return *p;
+}
+template <typename T>
+__device__ inline void st_pop(T* p, T v)
+{
+    *p = v;
+}
+
+// A wave-uniform 64-bit value, made explicitly uniform (readfirstlane of
+// each half; the builtin returns int, so go through uint32_t before
+// widening or the low half would be sign-extended).
+__device__ inline uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Per-lane select of a 32-bit value by a wave-uniform 64-bit lane mask (bit
+// l picks b for lane l): one v_cndmask with the mask in an SGPR pair.
+__device__ inline uint32_t lane_select(uint32_t a, uint32_t b, uint64_t m)
+{
+    // m is wave-uniform by construction; readfirstlane makes that explicit
+    // so that it is held in an SGPR pair
+    const uint64_t ms = uniform_u64(m);
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(ms));
+    return r;
+}
+
+// The solid mask is read-only while a step runs: reading it through the
+// constant address space lets wave-uniform words come in by scalar loads.
+typedef const uint64_t __attribute__((address_space(4))) const_u64;
+
+__device__ inline uint64_t mask_word(const uint64_t* mask, long long i)
+{
+    return ((const const_u64*)mask)[i];
+}
+
+template <typename R>
+__device__ inline void inflow_eq_stored(const double* __restrict__ prof, const Geo& g, int face, int z, R rho0, R sc,
+                                        R* h)
+{
+    const double* p = prof + ((long long)face * g.nz + z) * 3;
+    equilibrium_shifted<R>(rho0, R(0), R(p[0]), R(p[1]), R(p[2]), h);
+#pragma unroll
+    for (int i = 0; i < NQ; i++) h[i] *= sc;
+}
+
+template <typename R>
+__device__ inline void add_stats(R* stats, const Geo& g, int x, int y, int z, R ux, R uy, R uz)
+{
+    const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+    stats[n] += ux;
+    stats[g.N + n] += uy;
+    stats[2 * g.N + n] += uz;
+    stats[3 * g.N + n] += ux * ux;
+    stats[4 * g.N + n] += uy * uy;
+    stats[5 * g.N + n] += uz * uz;
+}
+
+// ---------------------------------------------------------------- even step
+template <int K, bool STATS>
+__global__ void __launch_bounds__(256)
+k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof, Geo g,
+       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nbp)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    using T = typename C::store;
+    const long long wave = xcd_remap(nbp) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int cx = (int)(wave % g.ncx);
+    const long long row = wave / g.ncx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const int x = cx * 64 + lane;
+    const uint64_t wrow = mask_word(mask, row * g.wpr + cx);
+    if (x >= g.nx || ((wrow >> lane) & 1ull)) return;
+
+    const long long sb = g.S * (long long)sizeof(T);
+    char* base = (char*)f;
+    const uint32_t off = (uint32_t)((long long)x + (long long)g.pitch * row) * (uint32_t)sizeof(T);
+    R h[NQ];
+    const int inf = inflow_face_of(g, x, y, z);
+    if (inf >= 0) {
+        inflow_eq_stored<R>(prof, g, inf, z, P.rho0, R(C::SC), h);
+        if constexpr (STATS) {
+            const double* p = prof + ((long long)inf * g.nz + z) * 3;
+            add_stats<R>(stats, g, x, y, z, R(p[0]), R(p[1]), R(p[2]));
+        }
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            st_pop((T*)(base + I * sb + off), C::pack(h[opp(I)]));
+        });
+        return;
+    }
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        h[I] = C::raw(ld_pop((const T*)(base + I * sb + off)));
+    });
+    R drho, ux, uy, uz, tau;
+    collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        st_pop((T*)(base + I * sb + off), C::pack(h[opp(I)]));
+    });
+    if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+}
+
+// Waves the odd kernel below leaves to the general kernel (same test on
+// the host, see odd_wave_is_general in the runtime).
+__device__ inline bool odd_general_wave(const Geo& g, int cx, int y, int z)
+{
+    if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1) return true;
+    if (cx == 0 && g.face[0] != F_INFLOW) return true;
+    if (cx * 64 + 63 >= g.nx - 1 && g.face[1] != F_OUTFLOW) return true;
+    return false;
+}
+
+// ---------------------------------------------------------------- odd step
+template <int K, bool STATS>
+__global__ void __launch_bounds__(256)
+k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+      const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P,
+      typename Codec<K>::real* stats, long long nwaves, long long nbp)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    using T = typename C::store;
+    const long long wave = xcd_remap(nbp) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int cx = (int)(wave % g.ncx);
+    const long long row = wave / g.ncx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    if (odd_general_wave(g, cx, y, z)) return;
+    const int x = cx * 64 + lane;
+    const bool x_lo = (cx == 0);                   // lane 0 is an x- inflow cell
+    const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane lo is an x+ outflow cell
+    const int l_out = (g.nx - 1) - cx * 64;
+
+    // solid rows around this one: W[dz+1][dy+1] = words cx-1, cx, cx+1
+    uint64_t Wp[3][3], Wc[3][3], Wn[3][3];
+#pragma unroll
+    for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++) {
+            const long long w = ((long long)(y + dy) + (long long)g.ny * (z + dz)) * g.wpr + cx;
+            Wc[dz + 1][dy + 1] = mask_word(mask, w);
+            Wp[dz + 1][dy + 1] = cx > 0 ? mask_word(mask, w - 1) : 0ull;
+            Wn[dz + 1][dy + 1] = (cx + 1 < g.wpr) ? mask_word(mask, w + 1) : 0ull;
+        }
+    const uint64_t self_solid = Wc[1][1];
+    if (x >= g.nx || ((self_solid >> lane) & 1ull)) return;
+
+    // bounce mask of direction I: bit l set when lane l must use its own
+    // slot (solid neighbour, or an x-face lane's face-crossing direction)
+    auto bmask = [&](auto ic) -> uint64_t {
+        constexpr int I = decltype(ic)::value;
+        constexpr V3 c = dirv(I);
+        const uint64_t wc = Wc[1 - c.z][1 - c.y];
+        uint64_t m;
+        if constexpr (c.x == 1) m = (wc << 1) | (Wp[1 - c.z][1 - c.y] >> 63);
+        else if constexpr (c.x == -1) m = (wc >> 1) | (Wn[1 - c.z][1 - c.y] << 63);
+        else m = wc;
+        if constexpr (c.x == 1) { if (x_lo) m |= 1ull; }
+        if constexpr (c.x == -1) { if (x_hi) m |= 1ull << l_out; }
+        return m;
+    };
+    uint64_t any = 0;
+    sfor<1, NQ>([&](auto ic) { any |= bmask(ic); });
+    any = uniform_u64(any);
+
+    const long long sb = g.S * (long long)sizeof(T);
+    char* base = (char*)f;
+    const uint32_t off = (uint32_t)((long long)x + (long long)g.pitch * row) * (uint32_t)sizeof(T);
+    R h[NQ];
+    if (any == 0) {
+        // fast path: no solid neighbour, no face lane
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            const long long d = (long long)c.x + (long long)g.pitch * (c.y + (long long)g.ny * c.z);
+            const char* sbI = base + opp(I) * sb - d * (long long)sizeof(T);
+            h[I] = C::raw(ld_pop((const T*)(sbI + off)));
+        });
+        R drho, ux, uy, uz, tau;
+        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            const long long d = (long long)c.x + (long long)g.pitch * (c.y + (long long)g.ny * c.z);
+            char* sbI = base + opp(I) * sb - d * (long long)sizeof(T);
+            st_pop((T*)(sbI + off), C::pack(h[opp(I)]));
+        });
+        if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+        return;
+    }
+
+    // masked path: per direction, slot = own (x, I) where the mask bit is set,
+    // else (x - c_I, opp(I)); both addressed from the lower of the two slices
+    uint32_t so[NQ];
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if constexpr (I == 0) {
+            so[0] = off;
+        } else {
+            constexpr V3 c = dirv(I);
+            constexpr int lo = I < opp(I) ? I : opp(I);
+            const long long d = (long long)c.x + (long long)g.pitch * (c.y + (long long)g.ny * c.z);
+            const uint32_t on = off + (uint32_t)((opp(I) - lo) * sb - d * (long long)sizeof(T));
+            const uint32_t oo = off + (uint32_t)((I - lo) * sb);
+            so[I] = lane_select(on, oo, bmask(ic));
+        }
+    });
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int lo = I < opp(I) ? I : opp(I);
+        h[I] = C::raw(ld_pop((const T*)(base + lo * sb + so[I])));
+    });
+    const bool inflow_lane = x_lo && lane == 0;
+    const bool outflow_lane = x_hi && lane == l_out;
+    if (outflow_lane) {
+        // entering populations of the x+ outflow cell: the ghost plane
+        const long long fc = (long long)g.ny * g.nz;
+        const long long gi = g.ghost_off[1] + y + (long long)g.ny * z;
+        h[2] = C::raw(ghost[gi]);
+        h[8] = C::raw(ghost[gi + fc]);
+        h[10] = C::raw(ghost[gi + 2 * fc]);
+        h[14] = C::raw(ghost[gi + 3 * fc]);
+        h[16] = C::raw(ghost[gi + 4 * fc]);
+    }
+    R ux, uy, uz;
+    if (inflow_lane) {
+        inflow_eq_stored<R>(prof, g, 0, z, P.rho0, R(C::SC), h);
+        const double* p = prof + (long long)z * 3;
+        ux = R(p[0]);
+        uy = R(p[1]);
+        uz = R(p[2]);
+    } else {
+        R drho, tau;
+        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+    }
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int lo = I < opp(I) ? I : opp(I);
+        st_pop((T*)(base + lo * sb + so[I]), C::pack(h[opp(I)]));
+    });
+    if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+}
+
+template <int K>
+static Phys<typename Codec<K>::real> phys_from(const DevCtx& d)
+{
+    using R = typename Codec<K>::real;
+    Phys<R> P;
+    P.tau0 = R(d.tau0);
+    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
+    P.rho0 = R(d.rho0);
+    for (int a = 0; a < 3; a++) P.F[a] = R(d.force[a]);
+    P.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+    return P;
+}
+
+template <int K>
+static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_t s)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
+    const long long nb = (nwaves + 3) / 4;
+    const long long nbp = (nb + 7) / 8 * 8;
+    const Phys<R> P = phys_from<K>(d);
+    auto* f = (typename C::store*)d.f;
+    if (!odd) {
+        if (stats)
+            hipLaunchKernelGGL((k_even<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, d.g, P,
+                               (R*)stats, nwaves, nbp);
+        else
+            hipLaunchKernelGGL((k_even<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, d.g, P,
+                               (R*)stats, nwaves, nbp);
+        return hipGetLastError();
+    }
+    const auto* gh = (const typename C::store*)d.ghost;
+    if (stats)
+        hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, gh, d.g, P,
+                           (R*)stats, nwaves, nbp);
+    else
+        hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, gh, d.g, P,
+                           (R*)stats, nwaves, nbp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_general_odd(d, stats, s);
+}
+
+hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s)
+{
+    switch (d.codec) {
+        case 0: return launch_fused<0>(d, odd, stats, s);
+        case 1: return launch_fused<1>(d, odd, stats, s);
+        case 2: return launch_fused<2>(d, odd, stats, s);
+        case 3: return launch_fused<3>(d, odd, stats, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lbm

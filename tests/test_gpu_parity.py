@@ -110,13 +110,20 @@ def test_boundary_matrix_stepwise_f64(fi, dims):
         assert err <= 1e-12, f"step {step}: relative error {err}"
 
 
-def test_ragged_multichunk_fast_path_f64():
-    """nx = 200: chunks 0..3 of 64 cells, two interior chunks take the fast
-    path, the last one is a ragged tail; solids on some rows only."""
+@pytest.mark.parametrize("layout", ["blocks", "chunk_edges"])
+def test_ragged_multichunk_fast_path_f64(layout):
+    """nx = 200: chunks 0..3 of 64 cells, interior chunks take the fast path
+    where no solid is near, the last chunk is a ragged tail; solids next to
+    high lanes (bit 31 and above of the lane masks) and at chunk edges."""
     nx, ny, nz = 200, 7, 6
     solid = np.zeros((nz, ny, nx), np.uint8)
-    solid[1:3, 2:4, 150:160] = 1
-    solid[4, 5, 30] = 1
+    if layout == "blocks":
+        solid[1:3, 2:4, 150:160] = 1
+        solid[4, 5, 30] = 1
+    else:
+        for x in (31, 32, 62, 63, 64, 127, 128, 191, 192, 198):
+            solid[2 + x % 3, 1 + x % 5, x] = 1
+        solid[3, 3, 40:50] = 1
     w = small_workload(nx, ny, nz, ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip"),
                        solid=solid)
     o = oracle_for(w)
