@@ -197,19 +197,16 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
     }
 }
 
+// Adjoint of one cell on the general path (every boundary rule).
 template <int K>
-__global__ void __launch_bounds__(256)
-k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
-          typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask, Geo g,
-          Phys<typename Codec<K>::real> P)
+__device__ inline void adjoint_cell(const typename Codec<K>::store* __restrict__ f_t,
+                                    const typename Codec<K>::real* __restrict__ lam_next,
+                                    typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
+                                    const Geo& g, const Phys<typename Codec<K>::real>& P, int x, int y, int z)
 {
     using C = Codec<K>;
     using R = typename C::real;
-    const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
-    const int x = (int)(n % g.nx);
-    const long long row = n / g.nx;
-    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const long long n = cidx(g, x, y, z);
     if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) {
 #pragma unroll
         for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] = R(0);
@@ -225,6 +222,90 @@ k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec
     collision_transpose<R>(h, ls, P);
 #pragma unroll
     for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] = ls[j];
+}
+
+// General path over a list of cells (the two-layer shell next to the faces).
+template <int K>
+__global__ void __launch_bounds__(256)
+k_adjoint_cells(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
+                typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask, Geo g,
+                Phys<typename Codec<K>::real> P, const unsigned* __restrict__ cells, long long ncells)
+{
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= ncells) return;
+    const long long n = cells[t];
+    const int x = (int)(n % g.nx);
+    const long long row = n / g.nx;
+    adjoint_cell<K>(f_t, lam_next, lam, mask, g, P, x, (int)(row % g.ny), (int)(row / g.ny));
+}
+
+// Cells of main_box(g, 1): the transposed streaming reduces to
+// lam*_k = lam_next(x + c_k, k), or lam_next(x, opp(k)) when x + c_k is
+// solid or beyond a WALL face (halfway bounce-back transposed).  One wave is one
+// 64-cell chunk of a row; the slot of each direction is one shared lane
+// offset plus a wave-uniform base, selected per lane by the solid lane mask.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
+               typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask, Geo g,
+               Phys<typename Codec<K>::real> P, long long nwaves)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    using T = typename C::store;
+    const long long wave = blockIdx.x * 4ll + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int cx = (int)(wave % g.ncx);
+    const long long row = wave / g.ncx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const Box B = main_box(g, 1);
+    if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
+    const int x = cx * 64 + lane;
+    RowWin W;
+    load_rows(W, mask, g, cx, y, z);
+    if (x < B.x0 || x > B.x1) return;
+    const long long cell = (long long)x + (long long)g.nx * row;
+    const long long sb = g.N * (long long)sizeof(R);
+    const uint32_t off = (uint32_t)cell * (uint32_t)sizeof(R);
+    const char* lbase = (const char*)lam_next;
+    if ((W.c[1][1] >> lane) & 1ull) {
+#pragma unroll
+        for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = R(0);
+        return;
+    }
+    uint64_t any = 0;
+    adj_static_for<1, NQ>([&](auto ic) { any |= solid_src_mask<decltype(ic)::value>(W); });
+    any = uniform_u64(any);
+    R ls[NQ], h[NQ];
+    if (any == 0) {
+        adj_static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+            ls[opp(I)] = *(const R*)(lbase + opp(I) * sb - d * (long long)sizeof(R) + off);
+        });
+    } else {
+        adj_static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (I == 0) {
+                ls[0] = *(const R*)(lbase + off);
+            } else {
+                constexpr V3 c = dirv(I);
+                constexpr int lo = I < opp(I) ? I : opp(I);
+                const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+                const uint32_t on = off + (uint32_t)((opp(I) - lo) * sb - d * (long long)sizeof(R));
+                const uint32_t oo = off + (uint32_t)((I - lo) * sb);
+                const uint32_t so = lane_select(on, oo, solid_src_mask<I>(W));
+                ls[opp(I)] = *(const R*)(lbase + lo * sb + so);
+            }
+        });
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + cell]);
+    collision_transpose<R>(h, ls, P);
+#pragma unroll
+    for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = ls[j];
 }
 
 // dL/du_in(face F, height z): one block per z, a fixed-order tree over the
@@ -341,8 +422,13 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
                                d.prof, g, P, F, (R*)g_inflow);
         }
     }
-    hipLaunchKernelGGL((k_adjoint<K>), dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, s,
-                       (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P);
+    const long long nwaves = (long long)g.ncx * g.ny * g.nz;
+    hipLaunchKernelGGL((k_adjoint_main<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
+                       (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, nwaves);
+    if (d.adj_list_n > 0)
+        hipLaunchKernelGGL((k_adjoint_cells<K>), dim3((unsigned)((d.adj_list_n + 255) / 256)), dim3(256), 0, s,
+                           (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,
+                           d.adj_list_n);
     if (probe_src && np > 0)
         hipLaunchKernelGGL((k_adjoint_probes<K>), dim3(1), dim3(64), 0, s, (const typename C::store*)f_t, (R*)lam,
                            d.mask, g, P, probes, np, (const R*)probe_src);

@@ -439,10 +439,12 @@ __device__ inline float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrt
 // --------------------------------------------------------------------------
 // rho - rho0 and u of stored shifts h (SC times the true shifts), in the
 // summation order of collide_pairs, so diagnostics match the collision bit
-// for bit.
+// for bit.  Contraction is off and every fused multiply-add is explicit, so
+// the arithmetic is the same in every kernel that inlines it.
 template <typename R, int SC>
 __device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz)
 {
+#pragma clang fp contract(off)
     constexpr R isc = R(1) / R(SC);
     const R s1 = h[1] + h[2], d1 = h[1] - h[2];
     const R s2 = h[3] + h[4], d2 = h[3] - h[4];
@@ -459,14 +461,15 @@ __device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& u
     const R jz = ((d3 + d5) + (d6 - d8)) - d9;
     drho = drs * isc;
     const R irho = fast_rcp<R>(P.rho0 + drho);
-    ux = (jx * isc + R(0.5) * P.F[0]) * irho;
-    uy = (jy * isc + R(0.5) * P.F[1]) * irho;
-    uz = (jz * isc + R(0.5) * P.F[2]) * irho;
+    ux = fma(jx, isc, R(0.5) * P.F[0]) * irho;
+    uy = fma(jy, isc, R(0.5) * P.F[1]) * irho;
+    uz = fma(jz, isc, R(0.5) * P.F[2]) * irho;
 }
 
 template <typename R, int SC>
 __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R& uy, R& uz, R& tau_o)
 {
+#pragma clang fp contract(off)
     constexpr R isc = R(1) / R(SC);
     const R s1 = h[1] + h[2], d1 = h[1] - h[2];
     const R s2 = h[3] + h[4], d2 = h[3] - h[4];
@@ -488,36 +491,39 @@ __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R
     const R drho = drs * isc;
     const R rho = P.rho0 + drho;
     const R irho = fast_rcp<R>(rho);
-    ux = (jx * isc + R(0.5) * P.F[0]) * irho;
-    uy = (jy * isc + R(0.5) * P.F[1]) * irho;
-    uz = (jz * isc + R(0.5) * P.F[2]) * irho;
+    ux = fma(jx, isc, R(0.5) * P.F[0]) * irho;
+    uy = fma(jy, isc, R(0.5) * P.F[1]) * irho;
+    uz = fma(jz, isc, R(0.5) * P.F[2]) * irho;
+    // Pi = M - (drho/3) I - rho u u  (exact D3Q19 identity for sum c c feq)
     const R t3 = drho * R(1.0 / 3.0);
     const R rux = rho * ux, ruy = rho * uy;
-    const R pxx = (mxx * isc - t3) - rux * ux;
-    const R pyy = (myy * isc - t3) - ruy * uy;
-    const R pzz = (mzz * isc - t3) - rho * uz * uz;
-    const R pxy = mxy * isc - rux * uy;
-    const R pxz = mxz * isc - rux * uz;
-    const R pyz = myz * isc - ruy * uz;
-    const R pp = (pxx * pxx + pyy * pyy + pzz * pzz) + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
-    const R q = fast_sqrt<R>(R(2) * pp);
-    const R tau = R(0.5) * (P.tau0 + fast_sqrt<R>(P.tau0 * P.tau0 + P.ksmag * q * irho));
+    const R pxx = fma(-rux, ux, fma(mxx, isc, -t3));
+    const R pyy = fma(-ruy, uy, fma(myy, isc, -t3));
+    const R pzz = fma(-rho * uz, uz, fma(mzz, isc, -t3));
+    const R pxy = fma(-rux, uy, mxy * isc);
+    const R pxz = fma(-rux, uz, mxz * isc);
+    const R pyz = fma(-ruy, uz, myz * isc);
+    const R pd = fma(pxx, pxx, fma(pyy, pyy, pzz * pzz));
+    const R po = fma(pxy, pxy, fma(pxz, pxz, pyz * pyz));
+    const R q = fast_sqrt<R>(R(2) * fma(R(2), po, pd));
+    const R tau = R(0.5) * (P.tau0 + fast_sqrt<R>(fma(P.ksmag * q, irho, P.tau0 * P.tau0)));
     const R om = fast_rcp<R>(tau);
     const R om1 = R(1) - om;
     // heq_i = w_i [drho - 1.5 rho u.u] + w_i rho (4.5 e^2 +- 3 e), times SC
-    const R base = drho - R(1.5) * rho * (ux * ux + uy * uy + uz * uz);
+    const R usq = fma(ux, ux, fma(uy, uy, uz * uz));
+    const R base = fma(R(-1.5) * rho, usq, drho);
     const R a0 = om * R(SC) * weight<R>(0), af = om * R(SC) * weight<R>(1), ae = om * R(SC) * weight<R>(7);
     const R c0 = a0 * base, cf = af * base, ce = ae * base;
     const R bf = af * R(4.5) * rho, be = ae * R(4.5) * rho;
     const R gf = af * R(3) * rho, ge = ae * R(3) * rho;
-    h[0] = om1 * h[0] + c0;
+    h[0] = fma(om1, h[0], c0);
 #define LBM_PAIR(i, e, C, B, G)                 \
     {                                           \
         const R ee = (e);                       \
-        const R t = (B) * (ee * ee) + (C);      \
+        const R t = fma((B), ee * ee, (C));     \
         const R o = (G) * ee;                   \
-        h[i] = om1 * h[i] + (t + o);            \
-        h[i + 1] = om1 * h[i + 1] + (t - o);    \
+        h[i] = fma(om1, h[i], t + o);           \
+        h[i + 1] = fma(om1, h[i + 1], t - o);   \
     }
     LBM_PAIR(1, ux, cf, bf, gf)
     LBM_PAIR(3, uy, cf, bf, gf)
@@ -532,8 +538,8 @@ __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R
     if (P.has_force) {
         // Guo source (1 - w/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F, times SC
         const R pre = (R(1) - R(0.5) * om) * R(SC);
-        const R uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
-        h[0] += pre * weight<R>(0) * (R(-3) * uF);
+        const R uF = fma(ux, P.F[0], fma(uy, P.F[1], uz * P.F[2]));
+        h[0] = fma(pre * weight<R>(0), R(-3) * uF, h[0]);
 #pragma unroll
         for (int i = 1; i < NQ; i += 2) {
             const V3 c = dirv(i);
@@ -547,6 +553,114 @@ __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R
     }
     drho_o = drho;
     tau_o = tau;
+}
+
+// --------------------------------------------------------------------------
+// Wave-level helpers for kernels where one wave is one 64-cell chunk of a
+// row (x = 64 cx + lane): the bit-packed solid mask then gives, per row, one
+// 64-bit word whose bit l is lane l's cell.
+// --------------------------------------------------------------------------
+// The solid mask is read-only while a kernel runs: reading it through the
+// constant address space lets wave-uniform words come in by scalar loads.
+typedef const uint64_t __attribute__((address_space(4))) const_u64;
+
+__device__ inline uint64_t mask_word(const uint64_t* mask, long long i)
+{
+    return ((const const_u64*)mask)[i];
+}
+
+// A wave-uniform 64-bit value, made explicitly uniform (readfirstlane of
+// each half; the builtin returns int, so go through uint32_t before
+// widening or the low half would be sign-extended).
+__device__ inline uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Per-lane select of a 32-bit value by a wave-uniform 64-bit lane mask (bit
+// l picks b for lane l): one v_cndmask with the mask in an SGPR pair.
+__device__ inline uint32_t lane_select(uint32_t a, uint32_t b, uint64_t m)
+{
+    // m is wave-uniform by construction; readfirstlane makes that explicit
+    // so that it is held in an SGPR pair
+    const uint64_t ms = uniform_u64(m);
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(ms));
+    return r;
+}
+
+
+// Solid words of the 3 x 3 rows around (y, z) (each interior), chunks
+// cx - 1, cx, cx + 1 (0 beyond the row).  Index [dz + 1][dy + 1].
+struct RowWin {
+    uint64_t p[3][3], c[3][3], n[3][3];
+};
+
+// A WALL face acts as a layer of solid cells just outside the grid (halfway
+// bounce-back at the face plane is the same rule as at a solid neighbour),
+// so rows and columns beyond WALL faces read as all-solid words.  Callers
+// only ask for rows beyond WALL faces.
+__device__ inline void load_rows(RowWin& W, const uint64_t* mask, const Geo& g, int cx, int y, int z)
+{
+    const bool xm_wall = g.face[0] == F_WALL, xp_wall = g.face[1] == F_WALL;
+    const bool last = (cx + 1 >= g.wpr);
+    const int l_last = (g.nx - 1) - cx * 64;  // lane of x = nx - 1 when this chunk holds it
+    const uint64_t pad = (xp_wall && last && l_last < 63) ? (~0ull << (l_last + 1)) : 0ull;
+#pragma unroll
+    for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++) {
+            const int yy = y + dy, zz = z + dz;
+            if (yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) {
+                W.c[dz + 1][dy + 1] = W.p[dz + 1][dy + 1] = W.n[dz + 1][dy + 1] = ~0ull;
+                continue;
+            }
+            const long long w = ((long long)yy + (long long)g.ny * zz) * g.wpr + cx;
+            W.c[dz + 1][dy + 1] = mask_word(mask, w) | pad;
+            W.p[dz + 1][dy + 1] = cx > 0 ? mask_word(mask, w - 1) : (xm_wall ? ~0ull : 0ull);
+            W.n[dz + 1][dy + 1] = !last ? mask_word(mask, w + 1) : (xp_wall ? ~0ull : 0ull);
+        }
+}
+
+// The box of cells the fast kernels take (inclusive bounds): every cell at
+// least L layers inside each face, L = 0 for WALL faces (bounce-back, like
+// solid cells), 1 for FREESLIP and PERIODIC faces (their pulls remap), and
+// 1 (push) or 2 (adjoint: outflow copies and inflow cells reach one layer
+// further) for INFLOW and OUTFLOW faces.  The rest runs the general code.
+struct Box {
+    int x0, x1, y0, y1, z0, z1;
+};
+
+__host__ __device__ inline int face_layers(int kind, int adjoint)
+{
+    if (kind == F_WALL) return 0;
+    if (kind == F_INFLOW || kind == F_OUTFLOW) return adjoint ? 2 : 1;
+    return 1;
+}
+
+__host__ __device__ inline Box main_box(const Geo& g, int adjoint)
+{
+    Box b;
+    b.x0 = face_layers(g.face[0], adjoint);
+    b.x1 = g.nx - 1 - face_layers(g.face[1], adjoint);
+    b.y0 = face_layers(g.face[2], adjoint);
+    b.y1 = g.ny - 1 - face_layers(g.face[3], adjoint);
+    b.z0 = face_layers(g.face[4], adjoint);
+    b.z1 = g.nz - 1 - face_layers(g.face[5], adjoint);
+    return b;
+}
+
+// Bit l set when the pull source (64 cx + l) - c_I of direction I is solid.
+template <int I>
+__device__ inline uint64_t solid_src_mask(const RowWin& W)
+{
+    constexpr V3 c = dirv(I);
+    const uint64_t wc = W.c[1 - c.z][1 - c.y];
+    if constexpr (c.x == 1) return (wc << 1) | (W.p[1 - c.z][1 - c.y] >> 63);
+    else if constexpr (c.x == -1) return (wc >> 1) | (W.n[1 - c.z][1 - c.y] << 63);
+    else return wc;
 }
 
 // splitmix64 (Steele, Lea & Flood 2014): golden-gamma increment, then the

@@ -50,86 +50,16 @@ __device__ inline long long xcd_block(long long nblocks_padded)
     return (b & 7) * per + (b >> 3);
 }
 
-// --------------------------------------------------------------------------
-// Collide-and-stream step.
-//   MODE_EVEN / MODE_ODD: in place on f (src == dst, padded layout).
-//   MODE_PUSH: canonical src -> canonical dst (local read, scattered write).
-// STATS: add u and u^2 of the pre-collision state into acc [6][N].
-// --------------------------------------------------------------------------
+// Every boundary rule, per cell: the step of one cell (x, y, z) in any mode.
 template <int K, int MODE, bool STATS>
-__global__ void __launch_bounds__(256)
-k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
-       const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
-       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nblocks_padded,
-       const unsigned* __restrict__ wlist)
+__device__ inline void general_cell(typename Codec<K>::store* dst, const typename Codec<K>::store* src,
+                                    const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+                                    const typename Codec<K>::store* __restrict__ ghost, const Geo& g, const Lay& ls,
+                                    const Lay& ld, const Phys<typename Codec<K>::real>& P,
+                                    typename Codec<K>::real* stats, int x, int y, int z)
 {
     using C = Codec<K>;
     using R = typename C::real;
-    const long long blk = xcd_block(nblocks_padded);
-    long long wave = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= nwaves) return;
-    if (wlist) wave = wlist[wave];
-    const int lane = threadIdx.x & 63;
-    const int cx = (int)(wave % g.ncx);
-    const long long row = wave / g.ncx;
-    const int y = (int)(row % g.ny);
-    const int z = (int)(row / g.ny);
-    const int x = cx * 64 + lane;
-
-    // ---------------- uniform fast-path test ----------------
-    bool fast = (y >= 1) && (y <= g.ny - 2) && (z >= 1) && (z <= g.nz - 2) && (cx >= 1) && (cx * 64 + 63 <= g.nx - 2);
-    if (fast) {
-        uint64_t acc = 0;
-#pragma unroll
-        for (int dz = -1; dz <= 1; dz++)
-#pragma unroll
-            for (int dy = -1; dy <= 1; dy++) {
-                const uint64_t* w = mask + (long long)((y + dy) + (long long)g.ny * (z + dz)) * g.wpr + cx;
-                acc |= w[0] | (w[-1] >> 63) | (w[1] << 63);
-            }
-        fast = (acc == 0);
-    }
-
-    if (fast) {
-        const long long ns = cell_index(ls, g.ny, x, y, z);
-        const long long nd = cell_index(ld, g.ny, x, y, z);
-        R h[NQ];
-        static_for<0, NQ>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            constexpr V3 c = dirv(I);
-            long long idx;
-            if constexpr (MODE == MODE_ODD)
-                idx = (long long)opp(I) * ls.S + ns - (c.x + (long long)ls.pitch * (c.y + (long long)g.ny * c.z));
-            else
-                idx = (long long)I * ls.S + ns;
-            h[I] = C::raw(src[idx]);
-        });
-        R drho, ux, uy, uz, tau;
-        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
-        static_for<0, NQ>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            constexpr V3 c = dirv(I);
-            long long idx;
-            if constexpr (MODE == MODE_EVEN)
-                idx = (long long)I * ld.S + nd;
-            else
-                idx = (long long)opp(I) * ld.S + nd - (c.x + (long long)ld.pitch * (c.y + (long long)g.ny * c.z));
-            dst[idx] = C::pack(h[opp(I)]);
-        });
-        if constexpr (STATS) {
-            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
-            stats[n] += ux;
-            stats[g.N + n] += uy;
-            stats[2 * g.N + n] += uz;
-            stats[3 * g.N + n] += ux * ux;
-            stats[4 * g.N + n] += uy * uy;
-            stats[5 * g.N + n] += uz * uz;
-        }
-        return;
-    }
-
-    // ---------------- general path: every boundary rule, per lane ----------------
-    if (x >= g.nx) return;
     const long long ns = cell_index(ls, g.ny, x, y, z);
     const long long nd = cell_index(ld, g.ny, x, y, z);
     if (solid_at(mask, g, x, y, z)) {
@@ -216,6 +146,105 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
         stats[4 * g.N + n] += uy * uy;
         stats[5 * g.N + n] += uz * uz;
     }
+}
+
+// --------------------------------------------------------------------------
+// Collide-and-stream step.
+//   MODE_EVEN / MODE_ODD: in place on f (src == dst, padded layout).
+//   MODE_PUSH: canonical src -> canonical dst (local read, scattered write).
+// STATS: add u and u^2 of the pre-collision state into acc [6][N].
+// --------------------------------------------------------------------------
+template <int K, int MODE, bool STATS>
+__global__ void __launch_bounds__(256)
+k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
+       const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
+       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nblocks_padded,
+       const unsigned* __restrict__ wlist)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long blk = xcd_block(nblocks_padded);
+    long long wave = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    if (wlist) wave = wlist[wave];
+    const int lane = threadIdx.x & 63;
+    const int cx = (int)(wave % g.ncx);
+    const long long row = wave / g.ncx;
+    const int y = (int)(row % g.ny);
+    const int z = (int)(row / g.ny);
+    const int x = cx * 64 + lane;
+
+    // ---------------- uniform fast-path test ----------------
+    bool fast = (y >= 1) && (y <= g.ny - 2) && (z >= 1) && (z <= g.nz - 2) && (cx >= 1) && (cx * 64 + 63 <= g.nx - 2);
+    if (fast) {
+        uint64_t acc = 0;
+#pragma unroll
+        for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+            for (int dy = -1; dy <= 1; dy++) {
+                const uint64_t* w = mask + (long long)((y + dy) + (long long)g.ny * (z + dz)) * g.wpr + cx;
+                acc |= w[0] | (w[-1] >> 63) | (w[1] << 63);
+            }
+        fast = (acc == 0);
+    }
+
+    if (fast) {
+        const long long ns = cell_index(ls, g.ny, x, y, z);
+        const long long nd = cell_index(ld, g.ny, x, y, z);
+        R h[NQ];
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            long long idx;
+            if constexpr (MODE == MODE_ODD)
+                idx = (long long)opp(I) * ls.S + ns - (c.x + (long long)ls.pitch * (c.y + (long long)g.ny * c.z));
+            else
+                idx = (long long)I * ls.S + ns;
+            h[I] = C::raw(src[idx]);
+        });
+        R drho, ux, uy, uz, tau;
+        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            long long idx;
+            if constexpr (MODE == MODE_EVEN)
+                idx = (long long)I * ld.S + nd;
+            else
+                idx = (long long)opp(I) * ld.S + nd - (c.x + (long long)ld.pitch * (c.y + (long long)g.ny * c.z));
+            dst[idx] = C::pack(h[opp(I)]);
+        });
+        if constexpr (STATS) {
+            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+            stats[n] += ux;
+            stats[g.N + n] += uy;
+            stats[2 * g.N + n] += uz;
+            stats[3 * g.N + n] += ux * ux;
+            stats[4 * g.N + n] += uy * uy;
+            stats[5 * g.N + n] += uz * uz;
+        }
+        return;
+    }
+
+    // ---------------- general path: every boundary rule, per lane ----------------
+    if (x >= g.nx) return;
+    general_cell<K, MODE, STATS>(dst, src, mask, prof, ghost, g, ls, ld, P, stats, x, y, z);
+}
+
+// One cell on the general path, for a list of cells (thread per cell).
+template <int K, int MODE>
+__global__ void __launch_bounds__(256)
+k_cells(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
+        const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
+        Phys<typename Codec<K>::real> P, const unsigned* __restrict__ cells, long long ncells)
+{
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= ncells) return;
+    const long long n = cells[t];
+    const int x = (int)(n % g.nx);
+    const long long row = n / g.nx;
+    general_cell<K, MODE, false>(dst, src, mask, prof, ghost, g, ls, ld, P, (typename Codec<K>::real*)nullptr, x,
+                                 (int)(row % g.ny), (int)(row / g.ny));
 }
 
 // --------------------------------------------------------------------------
@@ -676,12 +705,16 @@ hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s)
     });
 }
 
-hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s)
+// General-path push for the listed cells (the face layer), canonical layout.
+hipError_t launch_push_cells(const DevCtx& d, const void* src, void* dst, hipStream_t s)
 {
+    if (d.push_list_n == 0) return hipSuccess;
     LBM_DISPATCH(d.codec, {
-        hipError_t e = step_dispatch<K>(d, MODE_PUSH, src, dst, canonical(d), canonical(d), nullptr, s);
-        if (e != hipSuccess) return e;
-        return launch_outflow_copy(d, dst, 1, s);
+        hipLaunchKernelGGL((k_cells<K, MODE_PUSH>), dim3(blocks_for(d.push_list_n, 256)), dim3(256), 0, s,
+                           (typename Codec<K>::store*)dst, (const typename Codec<K>::store*)src, d.mask, d.prof,
+                           (const typename Codec<K>::store*)d.ghost, d.g, canonical(d), canonical(d), phys_of<K>(d),
+                           d.push_list, d.push_list_n);
+        return hipGetLastError();
     });
 }
 

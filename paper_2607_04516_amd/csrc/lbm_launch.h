@@ -18,16 +18,23 @@ struct DevCtx {
     const double* prof;   // inflow profiles [6][nz][3]
     const unsigned* odd_list;  // waves of the odd step left to the general kernel
     long long odd_list_n;
+    const unsigned* push_list; // canonical indices of the face layer (general-path push)
+    long long push_list_n;
+    const unsigned* adj_list;  // canonical indices of the two-layer face shell (general-path adjoint)
+    long long adj_list_n;
     double tau0, c_smag, delta, rho0, force[3];
 };
 
 // Host copy of the odd kernel's test for waves it leaves to the general
 // kernel (k_odd in lbm_step.hip applies the same test).
-inline bool odd_wave_is_general(const Geo& g, int cx, int y, int z)
+// Rows on a y or z face other than WALL, and chunks holding an x-face cell
+// unless the x- face is INFLOW or WALL and the x+ face OUTFLOW or WALL.
+__host__ __device__ inline bool odd_wave_is_general(const Geo& g, int cx, int y, int z)
 {
-    if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1) return true;
-    if (cx == 0 && g.face[0] != F_INFLOW) return true;
-    if (cx * 64 + 63 >= g.nx - 1 && g.face[1] != F_OUTFLOW) return true;
+    if ((y == 0 && g.face[2] != F_WALL) || (y == g.ny - 1 && g.face[3] != F_WALL)) return true;
+    if ((z == 0 && g.face[4] != F_WALL) || (z == g.nz - 1 && g.face[5] != F_WALL)) return true;
+    if (cx == 0 && g.face[0] != F_INFLOW && g.face[0] != F_WALL) return true;
+    if (cx * 64 + 63 >= g.nx - 1 && g.face[1] != F_OUTFLOW && g.face[1] != F_WALL) return true;
     return false;
 }
 
@@ -35,6 +42,7 @@ hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s);
 hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s);
 hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s);
 hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s);
+hipError_t launch_push_cells(const DevCtx& d, const void* src, void* dst, hipStream_t s);
 hipError_t launch_outflow_ghost(const DevCtx& d, hipStream_t s);
 hipError_t launch_outflow_copy(const DevCtx& d, void* arr, int canonical_layout, hipStream_t s);
 hipError_t launch_init(const DevCtx& d, const double* u0_dev, double amp, uint64_t seed, hipStream_t s);

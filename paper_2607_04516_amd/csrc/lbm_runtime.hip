@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -35,6 +36,8 @@ struct lbm_ctx {
     double* red_partial = nullptr;
     double* red_out = nullptr;  // device [5]
     unsigned* odd_list = nullptr;
+    unsigned* push_list = nullptr;
+    unsigned* adj_list = nullptr;
     void* stats = nullptr;
     int stats_stride = 0;
     int64_t fluid = 0, interior = 0;
@@ -89,7 +92,8 @@ static void free_all(lbm_ctx* c)
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->ev_used = 0;
-    void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list};
+    void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
+                    c->push_list, c->adj_list};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -101,6 +105,8 @@ static void free_all(lbm_ctx* c)
     c->red_partial = nullptr;
     c->red_out = nullptr;
     c->odd_list = nullptr;
+    c->push_list = nullptr;
+    c->adj_list = nullptr;
 }
 
 static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
@@ -239,6 +245,34 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     }
     c->d.odd_list = c->odd_list;
     c->d.odd_list_n = (long long)olist.size();
+    // cells outside the fast kernels' boxes (main_box): general path
+    std::vector<unsigned> plist, alist;
+    for (int z = 0; z < g.nz; z++)
+        for (int y = 0; y < g.ny; y++)
+            for (int x = 0; x < g.nx; x++) {
+                const unsigned n = (unsigned)(x + (long long)g.nx * (y + (long long)g.ny * z));
+                const Box bp = main_box(g, 0), ba = main_box(g, 1);
+                if (x < bp.x0 || x > bp.x1 || y < bp.y0 || y > bp.y1 || z < bp.z0 || z > bp.z1) plist.push_back(n);
+                if (x < ba.x0 || x > ba.x1 || y < ba.y0 || y > ba.y1 || z < ba.z0 || z > ba.z1) alist.push_back(n);
+            }
+    if ((rc = device_alloc(c, (void**)&c->push_list, plist.size() * sizeof(unsigned), "cell list")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->adj_list, alist.size() * sizeof(unsigned), "cell list")) != LBM_OK) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    if (hipMemcpy(c->push_list, plist.data(), plist.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->adj_list, alist.data(), alist.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
+        g_create_error = "upload cell lists";
+        free_all(c);
+        delete c;
+        return LBM_EHIP;
+    }
+    c->d.push_list = c->push_list;
+    c->d.push_list_n = (long long)plist.size();
+    c->d.adj_list = c->adj_list;
+    c->d.adj_list_n = (long long)alist.size();
     c->prof_host.assign(18 * (size_t)g.nz, 0.0);
     hipError_t e = hipMemcpy(c->mask, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->prof, 0, 18 * (size_t)g.nz * sizeof(double));
@@ -540,6 +574,12 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
 {
     if (!c) return LBM_EINVAL;
     if (!f_t || !lam_next || !lam || lam == lam_next) return fail(c, LBM_EINVAL, "bad adjoint arguments");
+    {
+        // the adjoint kernels address two adjacent adjoint slices with 32-bit byte offsets
+        const long long real_bytes = c->p.storage == LBM_F64 ? 8 : 4;
+        if (2 * c->d.g.N * real_bytes >= (1ll << 32))
+            return fail(c, LBM_EINVAL, "grid too large for the adjoint (an adjoint slice must stay below 2 GiB)");
+    }
     if (probe_src && c->np == 0) return fail(c, LBM_ESTATE, "probe source without registered probes");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;

@@ -57,37 +57,6 @@ __device__ inline void st_pop(T* p, T v)
     *p = v;
 }
 
-// A wave-uniform 64-bit value, made explicitly uniform (readfirstlane of
-// each half; the builtin returns int, so go through uint32_t before
-// widening or the low half would be sign-extended).
-__device__ inline uint64_t uniform_u64(uint64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
-// Per-lane select of a 32-bit value by a wave-uniform 64-bit lane mask (bit
-// l picks b for lane l): one v_cndmask with the mask in an SGPR pair.
-__device__ inline uint32_t lane_select(uint32_t a, uint32_t b, uint64_t m)
-{
-    // m is wave-uniform by construction; readfirstlane makes that explicit
-    // so that it is held in an SGPR pair
-    const uint64_t ms = uniform_u64(m);
-    uint32_t r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(ms));
-    return r;
-}
-
-// The solid mask is read-only while a step runs: reading it through the
-// constant address space lets wave-uniform words come in by scalar loads.
-typedef const uint64_t __attribute__((address_space(4))) const_u64;
-
-__device__ inline uint64_t mask_word(const uint64_t* mask, long long i)
-{
-    return ((const const_u64*)mask)[i];
-}
-
 template <typename R>
 __device__ inline void inflow_eq_stored(const double* __restrict__ prof, const Geo& g, int face, int z, R rho0, R sc,
                                         R* h)
@@ -163,10 +132,7 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
 // the host, see odd_wave_is_general in the runtime).
 __device__ inline bool odd_general_wave(const Geo& g, int cx, int y, int z)
 {
-    if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1) return true;
-    if (cx == 0 && g.face[0] != F_INFLOW) return true;
-    if (cx * 64 + 63 >= g.nx - 1 && g.face[1] != F_OUTFLOW) return true;
-    return false;
+    return odd_wave_is_general(g, cx, y, z);
 }
 
 // ---------------------------------------------------------------- odd step
@@ -187,34 +153,20 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
     const int y = (int)(row % g.ny), z = (int)(row / g.ny);
     if (odd_general_wave(g, cx, y, z)) return;
     const int x = cx * 64 + lane;
-    const bool x_lo = (cx == 0);                   // lane 0 is an x- inflow cell
-    const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane lo is an x+ outflow cell
+    const bool x_lo = (cx == 0);                   // lane 0 is an x- inflow or wall cell
+    const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane l_out is an x+ outflow or wall cell
     const int l_out = (g.nx - 1) - cx * 64;
 
-    // solid rows around this one: W[dz+1][dy+1] = words cx-1, cx, cx+1
-    uint64_t Wp[3][3], Wc[3][3], Wn[3][3];
-#pragma unroll
-    for (int dz = -1; dz <= 1; dz++)
-#pragma unroll
-        for (int dy = -1; dy <= 1; dy++) {
-            const long long w = ((long long)(y + dy) + (long long)g.ny * (z + dz)) * g.wpr + cx;
-            Wc[dz + 1][dy + 1] = mask_word(mask, w);
-            Wp[dz + 1][dy + 1] = cx > 0 ? mask_word(mask, w - 1) : 0ull;
-            Wn[dz + 1][dy + 1] = (cx + 1 < g.wpr) ? mask_word(mask, w + 1) : 0ull;
-        }
-    const uint64_t self_solid = Wc[1][1];
-    if (x >= g.nx || ((self_solid >> lane) & 1ull)) return;
+    RowWin W;
+    load_rows(W, mask, g, cx, y, z);
+    if (x >= g.nx || ((W.c[1][1] >> lane) & 1ull)) return;
 
     // bounce mask of direction I: bit l set when lane l must use its own
     // slot (solid neighbour, or an x-face lane's face-crossing direction)
     auto bmask = [&](auto ic) -> uint64_t {
         constexpr int I = decltype(ic)::value;
         constexpr V3 c = dirv(I);
-        const uint64_t wc = Wc[1 - c.z][1 - c.y];
-        uint64_t m;
-        if constexpr (c.x == 1) m = (wc << 1) | (Wp[1 - c.z][1 - c.y] >> 63);
-        else if constexpr (c.x == -1) m = (wc >> 1) | (Wn[1 - c.z][1 - c.y] << 63);
-        else m = wc;
+        uint64_t m = solid_src_mask<I>(W);
         if constexpr (c.x == 1) { if (x_lo) m |= 1ull; }
         if constexpr (c.x == -1) { if (x_hi) m |= 1ull << l_out; }
         return m;
@@ -270,8 +222,8 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
         constexpr int lo = I < opp(I) ? I : opp(I);
         h[I] = C::raw(ld_pop((const T*)(base + lo * sb + so[I])));
     });
-    const bool inflow_lane = x_lo && lane == 0;
-    const bool outflow_lane = x_hi && lane == l_out;
+    const bool inflow_lane = x_lo && g.face[0] == F_INFLOW && lane == 0;
+    const bool outflow_lane = x_hi && g.face[1] == F_OUTFLOW && lane == l_out;
     if (outflow_lane) {
         // entering populations of the x+ outflow cell: the ghost plane
         const long long fc = (long long)g.ny * g.nz;
@@ -299,6 +251,79 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
         st_pop((T*)(base + lo * sb + so[I]), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+}
+
+// ---------------------------------------------------------------- push step
+// Out-of-place step on canonical (unpadded) arrays, src -> dst, for the
+// cells of main_box(g, 0): local read, collision, push of f*_opp(I) into
+// the slot the pull of I resolves to (own slot at solid neighbours and
+// across WALL faces).  The other face layers run the general per-cell code
+// afterwards (launch_push_cells), which overwrites what this kernel pushed
+// into inflow cells with their canonical equilibrium.  Solid cells get 0.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::store* __restrict__ dst,
+       const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P, long long nwaves)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    using T = typename C::store;
+    const long long wave = blockIdx.x * 4ll + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int cx = (int)(wave % g.ncx);
+    const long long row = wave / g.ncx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const Box B = main_box(g, 0);
+    if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
+    const int x = cx * 64 + lane;
+    RowWin W;
+    load_rows(W, mask, g, cx, y, z);
+    if (x < B.x0 || x > B.x1) return;
+    const long long sb = g.N * (long long)sizeof(T);
+    const uint32_t off = (uint32_t)((long long)x + (long long)g.nx * row) * (uint32_t)sizeof(T);
+    const char* sbase = (const char*)src;
+    char* dbase = (char*)dst;
+    if ((W.c[1][1] >> lane) & 1ull) {
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            st_pop((T*)(dbase + I * sb + off), C::pack(R(0)));
+        });
+        return;
+    }
+    uint64_t any = 0;
+    sfor<1, NQ>([&](auto ic) { any |= solid_src_mask<decltype(ic)::value>(W); });
+    any = uniform_u64(any);
+    R h[NQ];
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        h[I] = C::raw(ld_pop((const T*)(sbase + I * sb + off)));
+    });
+    R drho, ux, uy, uz, tau;
+    collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+    if (any == 0) {
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+            st_pop((T*)(dbase + opp(I) * sb - d * (long long)sizeof(T) + off), C::pack(h[opp(I)]));
+        });
+        return;
+    }
+    sfor<0, NQ>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if constexpr (I == 0) {
+            st_pop((T*)(dbase + off), C::pack(h[0]));
+        } else {
+            constexpr V3 c = dirv(I);
+            constexpr int lo = I < opp(I) ? I : opp(I);
+            const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+            const uint32_t on = off + (uint32_t)((opp(I) - lo) * sb - d * (long long)sizeof(T));
+            const uint32_t oo = off + (uint32_t)((I - lo) * sb);
+            const uint32_t so = lane_select(on, oo, solid_src_mask<I>(W));
+            st_pop((T*)(dbase + lo * sb + so), C::pack(h[opp(I)]));
+        }
+    });
 }
 
 template <int K>
@@ -343,6 +368,30 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_general_odd(d, stats, s);
+}
+
+template <int K>
+static hipError_t launch_push_k(const DevCtx& d, const void* src, void* dst, hipStream_t s)
+{
+    using C = Codec<K>;
+    const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
+    hipLaunchKernelGGL((k_push<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
+                       (const typename C::store*)src, (typename C::store*)dst, d.mask, d.g, phys_from<K>(d), nwaves);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_push_cells(d, src, dst, s)) != hipSuccess) return e;
+    return launch_outflow_copy(d, dst, 1, s);
+}
+
+hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s)
+{
+    switch (d.codec) {
+        case 0: return launch_push_k<0>(d, src, dst, s);
+        case 1: return launch_push_k<1>(d, src, dst, s);
+        case 2: return launch_push_k<2>(d, src, dst, s);
+        case 3: return launch_push_k<3>(d, src, dst, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s)
