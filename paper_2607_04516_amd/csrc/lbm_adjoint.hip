@@ -95,7 +95,8 @@ template <typename R>
 __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
 {
     R drho, ux, uy, uz, inv_rho;
-    moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+    moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
+    inv_rho = fast_rcp<R>(P.rho0 + drho);
     const R rho = P.rho0 + drho;
     R heq[NQ];
     equilibrium_shifted<R>(rho, drho, ux, uy, uz, heq);
@@ -391,7 +392,8 @@ __global__ void k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_
         R h[NQ];
         for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
         R drho, ux, uy, uz, inv_rho;
-        moments<R>(h, P, drho, ux, uy, uz, inv_rho);
+        moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
+    inv_rho = fast_rcp<R>(P.rho0 + drho);
         const R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
         const R su = sx * ux + sy * uy + sz * uz;
         for (int j = 0; j < NQ; j++) {

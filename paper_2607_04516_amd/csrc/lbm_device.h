@@ -322,96 +322,19 @@ __device__ inline Res resolve_full(const Geo& g, const uint64_t* __restrict__ ma
 template <typename R>
 __device__ inline void equilibrium_shifted(R rho, R drho, R ux, R uy, R uz, R* heq)
 {
-    const R usq15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
-    heq[0] = weight<R>(0) * (drho - rho * usq15);
+#pragma clang fp contract(off)
+    const R usq15 = R(1.5) * fma(ux, ux, fma(uy, uy, uz * uz));
+    heq[0] = weight<R>(0) * fma(-rho, usq15, drho);
 #pragma unroll
     for (int k = 1; k < NQ; k += 2) {
         const V3 c = dirv(k);
         const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
         const R w = weight<R>(k);
-        const R even = w * (drho + rho * (R(4.5) * e * e - usq15));
+        const R even = w * fma(rho, fma(R(4.5) * e, e, -usq15), drho);
         const R odd = w * rho * (R(3) * e);
         heq[k] = even + odd;
         heq[k + 1] = even - odd;
     }
-}
-
-// --------------------------------------------------------------------------
-// Local collision of one cell on shifted populations h (in place):
-//   rho = rho0 + sum h, rho u = sum c h (+ F/2)             (eq. D.1)
-//   Pi = sum c c (h - heq), Q = sqrt(2 Pi:Pi)                (eqs. D.8, D.10)
-//   tau_eff = (tau0 + sqrt(tau0^2 + 18 (C Delta)^2 Q / rho)) / 2   (eq. D.11)
-//   h*_i = h_i - (h_i - heq_i)/tau_eff (+ Guo source)        (eq. D.2)
-// Returns rho - rho0, u and tau_eff through the out parameters.
-// --------------------------------------------------------------------------
-// Moments of shifted populations (eq. D.1): rho - rho0 = sum h, and
-// u = (sum c h + F/2) / rho.  One fixed summation order, shared by the
-// collision and every diagnostic so that they agree to the last bit.
-template <typename R>
-__device__ inline void moments(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz, R& inv_rho)
-{
-    R d = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
-    d += ((h[8] + h[9]) + (h[10] + h[11])) + ((h[12] + h[13]) + (h[14] + h[15]));
-    d += (h[16] + h[17]) + h[18];
-    R jx = ((h[1] - h[2]) + (h[7] - h[8])) + ((h[9] - h[10]) + (h[13] - h[14])) + (h[15] - h[16]);
-    R jy = ((h[3] - h[4]) + (h[7] - h[8])) + ((h[11] - h[12]) + (h[14] - h[13])) + (h[17] - h[18]);
-    R jz = ((h[5] - h[6]) + (h[9] - h[10])) + ((h[11] - h[12]) + (h[16] - h[15])) + (h[18] - h[17]);
-    if (P.has_force) {
-        jx += R(0.5) * P.F[0];
-        jy += R(0.5) * P.F[1];
-        jz += R(0.5) * P.F[2];
-    }
-    inv_rho = R(1) / (P.rho0 + d);
-    drho = d;
-    ux = jx * inv_rho;
-    uy = jy * inv_rho;
-    uz = jz * inv_rho;
-}
-
-// --------------------------------------------------------------------------
-// Local collision of one cell on shifted populations h (in place):
-//   rho = rho0 + sum h, rho u = sum c h (+ F/2)             (eq. D.1)
-//   Pi = sum c c (h - heq), Q = sqrt(2 Pi:Pi)                (eqs. D.8, D.10)
-//   tau_eff = (tau0 + sqrt(tau0^2 + 18 (C Delta)^2 Q / rho)) / 2   (eq. D.11)
-//   h*_i = h_i - (h_i - heq_i)/tau_eff (+ Guo source)        (eq. D.2)
-// Returns rho - rho0, u and tau_eff through the out parameters.
-// --------------------------------------------------------------------------
-template <typename R>
-__device__ inline void collide(R* h, const Phys<R>& P, R& drho_out, R& ux, R& uy, R& uz, R& tau_out)
-{
-    R drho, inv_rho;
-    moments<R>(h, P, drho, ux, uy, uz, inv_rho);
-    const R rho = P.rho0 + drho;
-    R neq[NQ];
-    equilibrium_shifted<R>(rho, drho, ux, uy, uz, neq);
-#pragma unroll
-    for (int i = 0; i < NQ; i++) neq[i] = h[i] - neq[i];
-    const R pxx = ((neq[1] + neq[2]) + (neq[7] + neq[8])) + ((neq[9] + neq[10]) + (neq[13] + neq[14])) + (neq[15] + neq[16]);
-    const R pyy = ((neq[3] + neq[4]) + (neq[7] + neq[8])) + ((neq[11] + neq[12]) + (neq[13] + neq[14])) + (neq[17] + neq[18]);
-    const R pzz = ((neq[5] + neq[6]) + (neq[9] + neq[10])) + ((neq[11] + neq[12]) + (neq[15] + neq[16])) + (neq[17] + neq[18]);
-    const R pxy = (neq[7] + neq[8]) - (neq[13] + neq[14]);
-    const R pxz = (neq[9] + neq[10]) - (neq[15] + neq[16]);
-    const R pyz = (neq[11] + neq[12]) - (neq[17] + neq[18]);
-    const R pp = (pxx * pxx + pyy * pyy + pzz * pzz) + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
-    const R q = sqrt(R(2) * pp);
-    const R tau = R(0.5) * (P.tau0 + sqrt(P.tau0 * P.tau0 + P.ksmag * q * inv_rho));
-    const R omega = R(1) / tau;
-#pragma unroll
-    for (int i = 0; i < NQ; i++) h[i] = h[i] - omega * neq[i];
-    if (P.has_force) {
-        // Guo source (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F
-        const R uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
-        const R pre = R(1) - R(0.5) * omega;
-#pragma unroll
-        for (int i = 0; i < NQ; i++) {
-            const V3 c = dirv(i);
-            const R cu = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
-            const R cF = R(c.x) * P.F[0] + R(c.y) * P.F[1] + R(c.z) * P.F[2];
-            h[i] += pre * weight<R>(i) * (R(3) * (cF - uF) + R(9) * cu * cF);
-        }
-    }
-    drho_out = drho;
-    tau_out = tau;
 }
 
 // Fast reciprocal and square root: hardware v_rcp_f32 / v_sqrt_f32 (about
