@@ -41,7 +41,7 @@ class _Cfg(ctypes.Structure):
                 ("face", ctypes.c_int32 * 6),
                 ("tau0", ctypes.c_double), ("c_smag", ctypes.c_double),
                 ("delta", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("force", ctypes.c_double * 3)]
+                ("force", ctypes.c_double * 3), ("omega", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -114,7 +114,7 @@ class Oracle:
     """One configured oracle lattice (geometry, faces, collision parameters)."""
 
     def __init__(self, nx, ny, nz, faces, tau0, c_smag=0.0, delta=1.0, rho0=1.0,
-                 force=(0.0, 0.0, 0.0), solid=None, inflow=None):
+                 force=(0.0, 0.0, 0.0), solid=None, inflow=None, omega=(0.0, 0.0, 0.0)):
         self.shape = (nz, ny, nx)
         self.cfg = _Cfg()
         self.cfg.nx, self.cfg.ny, self.cfg.nz = nx, ny, nz
@@ -123,6 +123,7 @@ class Oracle:
         self.cfg.tau0, self.cfg.c_smag, self.cfg.delta, self.cfg.rho0 = tau0, c_smag, delta, rho0
         for a in range(3):
             self.cfg.force[a] = float(force[a])
+            self.cfg.omega[a] = float(omega[a])
         self.solid = np.zeros(self.shape, np.uint8) if solid is None else \
             np.ascontiguousarray(solid, np.uint8).reshape(self.shape)
         self.inflow = np.zeros((6, nz, 3), np.float64)

@@ -82,6 +82,7 @@ typedef struct {
     double delta;   /* filter width Delta in lattice units */
     double rho0;    /* reference density of inflow cells */
     double force[3];/* uniform body force per unit volume (Guo scheme) */
+    double omega[3];/* Earth rotation vector in lattice units (App. E), ENU frame */
 } or_cfg;
 
 /* Error state of the last call (0 = fine). */
@@ -113,17 +114,31 @@ void or_equilibrium(double rho, const double *u, double *feq)
     }
 }
 
+/* Total body force on a cell: the uniform force plus the Coriolis force
+ * (App. E) F_c = -2 rho Omega x u0, with u0 = (sum c f)/rho the velocity
+ * recovered from the populations before the force enters.  The paper
+ * prints +2 Omega x v; the rotating-frame acceleration is -2 Omega x v,
+ * which is the reading taken here. */
+static void body_force(const or_cfg *g, double rho, const double *m, double *F)
+{
+    double u0[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+    const double *w = g->omega;
+    double wxu[3] = {w[1] * u0[2] - w[2] * u0[1], w[2] * u0[0] - w[0] * u0[2], w[0] * u0[1] - w[1] * u0[0]};
+    for (int a = 0; a < 3; a++) F[a] = g->force[a] - 2.0 * rho * wxu[a];
+}
+
 /* Moments (App. D, zeroth and first moment equation):
  *   rho = sum_i f_i,  rho u = sum_i c_i f_i  (+ F/2 with a body force, Guo). */
 void or_moments(const or_cfg *g, const double *f, double *rho, double *u)
 {
-    double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+    double r = 0.0, m[3] = {0.0, 0.0, 0.0}, F[3];
     for (int i = 0; i < NQ; i++) {
         r += f[i];
         for (int a = 0; a < 3; a++) m[a] += CV[i][a] * f[i];
     }
     *rho = r;
-    for (int a = 0; a < 3; a++) u[a] = (m[a] + 0.5 * g->force[a]) / r;
+    body_force(g, r, m, F);
+    for (int a = 0; a < 3; a++) u[a] = (m[a] + 0.5 * F[a]) / r;
 }
 
 /* Effective relaxation time (App. D, closed-form tau_eff equation):
@@ -159,8 +174,13 @@ double or_q_invariant(const double *f, const double *feq, double *pi /* [3][3] o
  * forcing as cited in App. E).  Returns tau_eff. */
 double or_collide(const or_cfg *g, const double *f, double *fstar, double *rho_out, double *u_out)
 {
-    double rho, u[3], feq[NQ];
+    double rho, u[3], feq[NQ], F[3], m[3];
     or_moments(g, f, &rho, u);
+    for (int a = 0; a < 3; a++) {
+        m[a] = 0.0;
+        for (int i = 0; i < NQ; i++) m[a] += CV[i][a] * f[i];
+    }
+    body_force(g, rho, m, F);
     or_equilibrium(rho, u, feq);
     double q = or_q_invariant(f, feq, NULL);
     double tau = or_tau_eff(g->tau0, g->c_smag, g->delta, q, rho);
@@ -170,7 +190,7 @@ double or_collide(const or_cfg *g, const double *f, double *fstar, double *rho_o
         double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
         double src = 0.0;
         for (int a = 0; a < 3; a++)
-            src += (3.0 * (CV[i][a] - u[a]) + 9.0 * cu * CV[i][a]) * g->force[a];
+            src += (3.0 * (CV[i][a] - u[a]) + 9.0 * cu * CV[i][a]) * F[a];
         src *= (1.0 - 0.5 * omega) * weight(i);
         fstar[i] = f[i] - omega * (f[i] - feq[i]) + src;
     }
@@ -473,8 +493,11 @@ void or_mass(const or_cfg *g, const uint8_t *solid, const double *f, double *mas
 void or_collide_jacobian(const or_cfg *g, const double *f, double *J)
 {
     const double cs2 = 1.0 / 3.0;
-    double rho, u[3], feq[NQ], pi[9];
+    double rho, u[3], feq[NQ], pi[9], m[3] = {0.0, 0.0, 0.0}, F[3];
     or_moments(g, f, &rho, u);
+    for (int a = 0; a < 3; a++)
+        for (int i = 0; i < NQ; i++) m[a] += CV[i][a] * f[i];
+    body_force(g, rho, m, F);
     or_equilibrium(rho, u, feq);
     double q = or_q_invariant(f, feq, pi);
     double tau = or_tau_eff(g->tau0, g->c_smag, g->delta, q, rho);
@@ -483,10 +506,18 @@ void or_collide_jacobian(const or_cfg *g, const double *f, double *J)
     double K = 2.0 * cd * cd / (cs2 * cs2);
     double D = g->tau0 * g->tau0 + K * q / rho;
 
-    /* d u_a / d f_j = (c_ja - u_a) / rho   (rho u = sum c f + F/2) */
-    double du[3][NQ];
+    /* The Coriolis part of F is -2 Omega x m with m = sum c f, so
+     * d F_a / d f_j = -2 (Omega x c_j)_a, and with rho u = m + F/2:
+     * d u_a / d f_j = (c_ja + dF_a/df_j / 2 - u_a) / rho */
+    double dF[3][NQ], du[3][NQ];
+    const double *w = g->omega;
+    for (int j = 0; j < NQ; j++) {
+        dF[0][j] = -2.0 * (w[1] * CV[j][2] - w[2] * CV[j][1]);
+        dF[1][j] = -2.0 * (w[2] * CV[j][0] - w[0] * CV[j][2]);
+        dF[2][j] = -2.0 * (w[0] * CV[j][1] - w[1] * CV[j][0]);
+    }
     for (int a = 0; a < 3; a++)
-        for (int j = 0; j < NQ; j++) du[a][j] = (CV[j][a] - u[a]) / rho;
+        for (int j = 0; j < NQ; j++) du[a][j] = (CV[j][a] + 0.5 * dF[a][j] - u[a]) / rho;
 
     /* d feq_i / d f_j = feq_i / rho + sum_a (d feq_i / d u_a) (d u_a / d f_j) */
     double dfeq[NQ][NQ];
@@ -527,11 +558,13 @@ void or_collide_jacobian(const or_cfg *g, const double *f, double *J)
     for (int i = 0; i < NQ; i++) {
         double e = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
         double B = 0.0;
-        for (int a = 0; a < 3; a++) B += (3.0 * (CV[i][a] - u[a]) + 9.0 * e * CV[i][a]) * g->force[a];
+        for (int a = 0; a < 3; a++) B += (3.0 * (CV[i][a] - u[a]) + 9.0 * e * CV[i][a]) * F[a];
         for (int j = 0; j < NQ; j++) {
             double dB = 0.0;
             double cdu = CV[i][0] * du[0][j] + CV[i][1] * du[1][j] + CV[i][2] * du[2][j];
-            for (int a = 0; a < 3; a++) dB += g->force[a] * (-3.0 * du[a][j] + 9.0 * CV[i][a] * cdu);
+            for (int a = 0; a < 3; a++)
+                dB += F[a] * (-3.0 * du[a][j] + 9.0 * CV[i][a] * cdu) +
+                      (3.0 * (CV[i][a] - u[a]) + 9.0 * e * CV[i][a]) * dF[a][j];
             double dS = -0.5 * domega[j] * weight(i) * B + (1.0 - 0.5 * omega) * weight(i) * dB;
             double kd = (i == j) ? 1.0 : 0.0;
             J[i * NQ + j] = kd - domega[j] * (f[i] - feq[i]) - omega * (kd - dfeq[i][j]) + dS;
@@ -602,8 +635,14 @@ int or_adjoint_step(const or_cfg *g, const uint8_t *solid, const double *inflow,
         double fc[NQ], rho, u[3];
         for (int i = 0; i < NQ; i++) fc[i] = f_t[i * N + n];
         or_moments(g, fc, &rho, u);
-        for (int j = 0; j < NQ; j++)
-            for (int a = 0; a < 3; a++) lam[j * N + n] += probe_src[3 * k + a] * (CV[j][a] - u[a]) / rho;
+        const double *w = g->omega;
+        for (int j = 0; j < NQ; j++) {
+            /* d u / d f_j = (c_j - Omega x c_j - u) / rho (Coriolis part of F/2) */
+            double oc[3] = {w[1] * CV[j][2] - w[2] * CV[j][1], w[2] * CV[j][0] - w[0] * CV[j][2],
+                            w[0] * CV[j][1] - w[1] * CV[j][0]};
+            for (int a = 0; a < 3; a++)
+                lam[j * N + n] += probe_src[3 * k + a] * (CV[j][a] - oc[a] - u[a]) / rho;
+        }
     }
     return 0;
 }

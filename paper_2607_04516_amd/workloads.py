@@ -140,6 +140,7 @@ class Workload:
     force: tuple = (0.0, 0.0, 0.0)
     probes: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
     heights: np.ndarray | None = None
+    omega: tuple = (0.0, 0.0, 0.0)   # Earth rotation vector in lattice units (grid frame)
 
     @property
     def cells(self):

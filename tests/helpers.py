@@ -11,7 +11,7 @@ FACE_NUM = {"periodic": oracle.PERIODIC, "inflow": oracle.INFLOW_EQ, "outflow": 
 def oracle_for(w: workloads.Workload):
     faces = [FACE_NUM[f] if isinstance(f, str) else int(f) for f in w.faces]
     o = oracle.Oracle(w.nx, w.ny, w.nz, faces, tau0=w.tau0, c_smag=w.c_smag, delta=w.delta,
-                      force=w.force, solid=w.solid, inflow=w.inflow)
+                      force=w.force, solid=w.solid, inflow=w.inflow, omega=w.omega)
     return o
 
 
@@ -20,14 +20,16 @@ def oracle_init(o, w):
 
 
 def small_workload(nx, ny, nz, faces, solid=None, tau0=0.52, c_smag=0.1, u=(0.04, 0.01, 0.0),
-                   storage="f64", force=(0.0, 0.0, 0.0), noise=1e-3, seed=5, inflow_faces=None):
+                   storage="f64", force=(0.0, 0.0, 0.0), noise=1e-3, seed=5, inflow_faces=None,
+                   omega=(0.0, 0.0, 0.0)):
     """Tiny workload with uniform velocity on every inflow face."""
     solid = np.zeros((nz, ny, nx), np.uint8) if solid is None else solid
     prof = workloads.uniform_profile(nz, u)
     fn = [f if isinstance(f, str) else {v: k for k, v in FACE_NUM.items()}[f] for f in faces]
     inflow = {k: prof.copy() for k, f in enumerate(fn) if f == "inflow"}
     return workloads.Workload(f"small_{nx}x{ny}x{nz}", nx, ny, nz, tuple(fn), tau0, c_smag, storage, 10,
-                              solid, inflow, prof.copy(), noise_amp=noise, noise_seed=seed, force=force)
+                              solid, inflow, prof.copy(), noise_amp=noise, noise_seed=seed, force=force,
+                              omega=tuple(omega))
 
 
 def fluid_mask(w):

@@ -24,10 +24,11 @@ def _cell(seed, rho=1.01, u=(0.04, -0.02, 0.03), amp=0.03):
     return oracle.equilibrium(rho, u) * (1.0 + amp * (rng.random(19) - 0.5))
 
 
+@pytest.mark.parametrize("omega", [(0.0, 0.0, 0.0), (0.0, 2e-3, 4e-3)])
 @pytest.mark.parametrize("force", [(0.0, 0.0, 0.0), (3e-4, -1e-4, 2e-4)])
 @pytest.mark.parametrize("c_smag", [0.0, 0.1, 0.3])
-def test_jacobian_matches_central_differences(force, c_smag):
-    o = oracle.Oracle(3, 3, 3, [oracle.PERIODIC] * 6, tau0=0.52, c_smag=c_smag, force=force)
+def test_jacobian_matches_central_differences(force, c_smag, omega):
+    o = oracle.Oracle(3, 3, 3, [oracle.PERIODIC] * 6, tau0=0.52, c_smag=c_smag, force=force, omega=omega)
     for seed in range(3):
         f = _cell(seed)
         J = o.collide_jacobian(f)
@@ -113,12 +114,14 @@ def _loss_and_grad(o, w, speeds, theta, probes, target, T, with_grad=True):
     return loss, np.concatenate([d_speeds, [d_theta]])
 
 
-def test_full_gradient_matches_finite_differences():
+@pytest.mark.parametrize("omega", [(0.0, 0.0, 0.0), (0.0, 3e-3, 6e-3)])
+def test_full_gradient_matches_finite_differences(omega):
     nx, ny, nz, T = 14, 8, 6, 12
     solid = np.zeros((nz, ny, nx), np.uint8)
     solid[0:3, 3:5, 6:8] = 1
     w = small_workload(nx, ny, nz, ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip"),
-                       solid=solid, tau0=0.55, c_smag=0.15, u=(0.05, 0.0, 0.0), noise=1e-3, seed=2)
+                       solid=solid, tau0=0.55, c_smag=0.15, u=(0.05, 0.0, 0.0), noise=1e-3, seed=2,
+                       omega=omega)
     o = oracle_for(w)
     probes = np.array([[9, 4, 4], [7, 2, 3], [11, 6, 1]], np.int32)
     speeds = workloads.power_law_speeds(nz, 0.05, 4.0, 0.25)
