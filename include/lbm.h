@@ -99,6 +99,19 @@ int lbm_create(const lbm_grid *grid, const uint8_t *solid, const lbm_params *par
  * the next step.  Errors: EINVAL (face not INFLOW_EQ, NULL u). */
 int lbm_set_inflow(lbm_ctx *ctx, int32_t face, const double *u);
 
+/* Set the rotation vector Omega of the frame in lattice units (App. E:
+ * Omega_lbm = Omega_SI * dt_SI, for the Earth Omega_SI = 7.292115e-5 rad/s
+ * times (0, cos phi, sin phi) in the east-north-up frame at latitude phi,
+ * rotated into the grid axes by the caller).  host double [3], components
+ * along x, y, z.  Every fluid cell then adds the Coriolis force
+ * F_c = -2 Omega x m (m = sum_i c_i f_i, the momentum recovered before the
+ * force enters) to the uniform body force in the Guo source; the sign is
+ * that of the rotating-frame acceleration.  Zero (the default) disables it.
+ * Applies to lbm_step, lbm_push_step, lbm_macros, the probes and
+ * lbm_adjoint_step from the next call on.  Errors: EINVAL (NULL, a
+ * component not finite or of magnitude above 0.25). */
+int lbm_set_rotation(lbm_ctx *ctx, const double *omega);
+
 /* Re-initialise the state at t = 0 to feq(rho0, u0[z] + noise) in fluid
  * cells.  u0: host double [nz][3], or NULL for params.u_init. */
 int lbm_reset(lbm_ctx *ctx, const double *u0);

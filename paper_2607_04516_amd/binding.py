@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p)]
 
 
-EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_reset", "lbm_step", "lbm_step_probed",
+EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_rotation", "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
            "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read"]
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
         "lbm_create": ([ctypes.POINTER(_Grid), P, ctypes.POINTER(_Params), ctypes.POINTER(P)], ctypes.c_int),
         "lbm_destroy": ([P], None),
         "lbm_set_inflow": ([P, I32, P], ctypes.c_int),
+        "lbm_set_rotation": ([P, P], ctypes.c_int),
         "lbm_reset": ([P, P], ctypes.c_int),
         "lbm_step": ([P, I64], ctypes.c_int),
         "lbm_step_probed": ([P, I64, P], ctypes.c_int),
@@ -176,6 +177,11 @@ class LBM:
         prof = np.ascontiguousarray(profile, np.float64).reshape(self.nz, 3)
         self._check(self.lib.lbm_set_inflow(self.ctx, int(face), prof.ctypes.data_as(ctypes.c_void_p)))
 
+    def set_rotation(self, omega):
+        """Rotation vector of the frame in lattice units (x, y, z); zero disables Coriolis."""
+        om = np.ascontiguousarray(omega, np.float64).reshape(3)
+        self._check(self.lib.lbm_set_rotation(self.ctx, om.ctypes.data_as(ctypes.c_void_p)))
+
     def reset(self, u0=None):
         if u0 is None:
             self._check(self.lib.lbm_reset(self.ctx, None))
@@ -277,5 +283,25 @@ def from_workload(w, storage=None, **kw):
               noise_seed=w.noise_seed, **kw)
     for face, prof in w.inflow.items():
         lat.set_inflow(face, prof)
+    if any(float(v) != 0.0 for v in w.omega):
+        lat.set_rotation(w.omega)
     lat.reset(w.u0)
     return lat
+
+
+OMEGA_EARTH = 7.292115e-5   # rad/s (App. E)
+
+
+def earth_rotation(latitude_deg: float, dt_si: float, grid_angle_deg: float = 0.0,
+                   omega_si: float = OMEGA_EARTH) -> np.ndarray:
+    """Rotation vector in lattice units for a grid at the given latitude
+    (App. E): Omega_ENU = Omega (0, cos phi, sin phi) in the east-north-up
+    frame, times the time step dt_si in seconds.  grid_angle_deg turns the
+    grid's x axis counterclockwise from east (the grid axes are east and
+    north turned by that angle), and the vector is expressed in grid axes."""
+    p = np.radians(latitude_deg)
+    enu = omega_si * dt_si * np.array([0.0, np.cos(p), np.sin(p)])
+    a = np.radians(grid_angle_deg)
+    ex = np.array([np.cos(a), np.sin(a), 0.0])     # grid x in ENU
+    ey = np.array([-np.sin(a), np.cos(a), 0.0])    # grid y in ENU
+    return np.array([enu @ ex, enu @ ey, enu[2]])

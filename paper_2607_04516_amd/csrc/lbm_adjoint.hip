@@ -94,8 +94,8 @@ __device__ inline R adj_gather(const R* lam_next, const uint64_t* __restrict__ m
 template <typename R>
 __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
 {
-    R drho, ux, uy, uz, inv_rho;
-    moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
+    R drho, ux, uy, uz, inv_rho, Fx, Fy, Fz;
+    moments_pairs<R, 1>(h, P, drho, ux, uy, uz, Fx, Fy, Fz);
     inv_rho = fast_rcp<R>(P.rho0 + drho);
     const R rho = P.rho0 + drho;
     R heq[NQ];
@@ -144,8 +144,8 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
         ty += R(c.y) * e * wl;
         tz += R(c.z) * e * wl;
         if (P.has_force) {
-            const R cF = R(c.x) * P.F[0] + R(c.y) * P.F[1] + R(c.z) * P.F[2];
-            const R uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+            const R cF = R(c.x) * Fx + R(c.y) * Fy + R(c.z) * Fz;
+            const R uF = ux * Fx + uy * Fy + uz * Fz;
             Pw += wl * (R(3) * (cF - uF) + R(9) * e * cF);
             ex += R(c.x) * cF * wl;
             ey += R(c.y) * cF * wl;
@@ -160,14 +160,28 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
     R Wx = omega * vx, Wy = omega * vy, Wz = omega * vz;
     if (P.has_force) {
         const R pre = R(1) - R(0.5) * omega;
-        Wx += pre * (R(-3) * P.F[0] * s0 + R(9) * ex);
-        Wy += pre * (R(-3) * P.F[1] * s0 + R(9) * ey);
-        Wz += pre * (R(-3) * P.F[2] * s0 + R(9) * ez);
+        Wx += pre * (R(-3) * Fx * s0 + R(9) * ex);
+        Wy += pre * (R(-3) * Fy * s0 + R(9) * ey);
+        Wz += pre * (R(-3) * Fz * s0 + R(9) * ez);
     }
     Wx *= inv_rho;
     Wy *= inv_rho;
     Wz *= inv_rho;
     const R Wu = Wx * ux + Wy * uy + Wz * uz;
+    // Coriolis: F = F0 - W2 x m, so d F / d f_j = D c_j with D v = -W2 x v,
+    // and rho du/df_j = M c_j - u with M = I + D/2.  The c_j-linear part of
+    // mu becomes c_j . (M^T W + (1 - omega/2) D^T V / rho), and D^T = -D
+    // (D is antisymmetric): M^T v = v + (W2 x v)/2, D^T v = W2 x v.
+    const R* W2 = P.W2;
+    if (P.has_rot) {
+        const R pre = (R(1) - R(0.5) * omega) * inv_rho;
+        const R ax = Wx + R(0.5) * (W2[1] * Wz - W2[2] * Wy) + pre * (W2[1] * vz - W2[2] * vy);
+        const R ay = Wy + R(0.5) * (W2[2] * Wx - W2[0] * Wz) + pre * (W2[2] * vx - W2[0] * vz);
+        const R az = Wz + R(0.5) * (W2[0] * Wy - W2[1] * Wx) + pre * (W2[0] * vy - W2[1] * vx);
+        Wx = ax;
+        Wy = ay;
+        Wz = az;
+    }
     // closure: -(d omega/d f_j)(G + P/2) = Z (dQ_j - Q/rho)
     R Z = R(0), twoq = R(0), base = R(0);
     R pux = 0, puy = 0, puz = 0;
@@ -178,7 +192,15 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
         puy = pxy * ux + pyy * uy + pyz * uz;
         puz = pxz * ux + pyz * uy + pzz * uz;
         const R upu = ux * pux + uy * puy + uz * puz;
-        base = upu - (pxx + pyy + pzz) / R(3);   // dQ_j = (2/Q)[c.Pi.c - 2 c.Pi u + base]
+        base = upu - (pxx + pyy + pzz) / R(3);   // dQ_j = (2/Q)[c.Pi.c - 2 (M c).Pi u + base]
+        if (P.has_rot) {                         // (M c).Pi u = c . M^T (Pi u)
+            const R ax = pux + R(0.5) * (W2[1] * puz - W2[2] * puy);
+            const R ay = puy + R(0.5) * (W2[2] * pux - W2[0] * puz);
+            const R az = puz + R(0.5) * (W2[0] * puy - W2[1] * pux);
+            pux = ax;
+            puy = ay;
+            puz = az;
+        }
     }
     const R Zq = Z * q * inv_rho;
     const R omA = omega * A;
@@ -375,8 +397,9 @@ k_adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next, const uin
     }
 }
 
-// Probe sources: lam(x_p) += src_p . (c_j - u)/rho, probes in order (one
-// thread, so repeated cells add deterministically).
+// Probe sources: lam(x_p) += src_p . (M c_j - u)/rho, probes in order (one
+// thread, so repeated cells add deterministically); M = I without rotation,
+// M c = c - Omega x c with it (the Coriolis part of F/2 in u).
 template <int K>
 __global__ void k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_t, typename Codec<K>::real* lam,
                                  const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P,
@@ -391,11 +414,20 @@ __global__ void k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_
         const long long n = cidx(g, x, y, z);
         R h[NQ];
         for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
-        R drho, ux, uy, uz, inv_rho;
+        R drho, ux, uy, uz;
         moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
-    inv_rho = fast_rcp<R>(P.rho0 + drho);
-        const R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
+        const R inv_rho = fast_rcp<R>(P.rho0 + drho);
+        R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
         const R su = sx * ux + sy * uy + sz * uz;
+        if (P.has_rot) {   // src . (M c) = (M^T src) . c, M^T s = s + (W2 x s)/2
+            const R* W2 = P.W2;
+            const R ax = sx + R(0.5) * (W2[1] * sz - W2[2] * sy);
+            const R ay = sy + R(0.5) * (W2[2] * sx - W2[0] * sz);
+            const R az = sz + R(0.5) * (W2[0] * sy - W2[1] * sx);
+            sx = ax;
+            sy = ay;
+            sz = az;
+        }
         for (int j = 0; j < NQ; j++) {
             const V3 c = dirv(j);
             lam[(long long)j * g.N + n] += (R(c.x) * sx + R(c.y) * sy + R(c.z) * sz - su) * inv_rho;
@@ -409,12 +441,7 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
 {
     using C = Codec<K>;
     using R = typename C::real;
-    Phys<R> P;
-    P.tau0 = R(d.tau0);
-    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
-    P.rho0 = R(d.rho0);
-    for (int a = 0; a < 3; a++) P.F[a] = R(d.force[a]);
-    P.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+    const Phys<R> P = phys_of<K>(d);
     const Geo& g = d.g;
     if (g_inflow) {
         // the inflow gradient reads lam_next before lam is written (lam != lam_next)

@@ -146,9 +146,30 @@ struct Phys {
     R tau0;
     R ksmag;       // 18 (C Delta)^2 = 2 (C Delta)^2 / cs^4
     R rho0;
-    R F[3];        // body force
-    int has_force;
+    R F[3];        // uniform body force
+    R W2[3];       // 2 Omega, Omega the rotation vector in lattice units (Coriolis)
+    int has_rot;   // W2 != 0
+    int has_force; // F != 0 or has_rot: the Guo source is applied
 };
+
+// Body force on one cell: the uniform force plus the Coriolis force of the
+// rotating frame (App. E), F_c = -2 rho Omega x u0 = -2 Omega x m, with
+// m = sum c f the momentum recovered before the force enters (the stored
+// shift w rho0 carries no momentum, so the shifted sums give m directly).
+// Contraction is off so every kernel that inlines this rounds alike.
+template <typename R>
+__device__ inline void cell_force(const Phys<R>& P, R mx, R my, R mz, R& Fx, R& Fy, R& Fz)
+{
+#pragma clang fp contract(off)
+    Fx = P.F[0];
+    Fy = P.F[1];
+    Fz = P.F[2];
+    if (P.has_rot) {
+        Fx = Fx - (P.W2[1] * mz - P.W2[2] * my);
+        Fy = Fy - (P.W2[2] * mx - P.W2[0] * mz);
+        Fz = Fz - (P.W2[0] * my - P.W2[1] * mx);
+    }
+}
 
 // Layout of one population array: index = dir*S + x + pitch*(y + ny*z).
 struct Lay {
@@ -365,7 +386,8 @@ __device__ inline float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrt
 // for bit.  Contraction is off and every fused multiply-add is explicit, so
 // the arithmetic is the same in every kernel that inlines it.
 template <typename R, int SC>
-__device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz)
+__device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz, R& Fx, R& Fy,
+                                     R& Fz)
 {
 #pragma clang fp contract(off)
     constexpr R isc = R(1) / R(SC);
@@ -384,9 +406,17 @@ __device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& u
     const R jz = ((d3 + d5) + (d6 - d8)) - d9;
     drho = drs * isc;
     const R irho = fast_rcp<R>(P.rho0 + drho);
-    ux = fma(jx, isc, R(0.5) * P.F[0]) * irho;
-    uy = fma(jy, isc, R(0.5) * P.F[1]) * irho;
-    uz = fma(jz, isc, R(0.5) * P.F[2]) * irho;
+    cell_force(P, jx * isc, jy * isc, jz * isc, Fx, Fy, Fz);
+    ux = fma(jx, isc, R(0.5) * Fx) * irho;
+    uy = fma(jy, isc, R(0.5) * Fy) * irho;
+    uz = fma(jz, isc, R(0.5) * Fz) * irho;
+}
+
+template <typename R, int SC>
+__device__ inline void moments_pairs(const R* h, const Phys<R>& P, R& drho, R& ux, R& uy, R& uz)
+{
+    R Fx, Fy, Fz;
+    moments_pairs<R, SC>(h, P, drho, ux, uy, uz, Fx, Fy, Fz);
 }
 
 template <typename R, int SC>
@@ -414,9 +444,11 @@ __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R
     const R drho = drs * isc;
     const R rho = P.rho0 + drho;
     const R irho = fast_rcp<R>(rho);
-    ux = fma(jx, isc, R(0.5) * P.F[0]) * irho;
-    uy = fma(jy, isc, R(0.5) * P.F[1]) * irho;
-    uz = fma(jz, isc, R(0.5) * P.F[2]) * irho;
+    R Fx, Fy, Fz;
+    cell_force(P, jx * isc, jy * isc, jz * isc, Fx, Fy, Fz);
+    ux = fma(jx, isc, R(0.5) * Fx) * irho;
+    uy = fma(jy, isc, R(0.5) * Fy) * irho;
+    uz = fma(jz, isc, R(0.5) * Fz) * irho;
     // Pi = M - (drho/3) I - rho u u  (exact D3Q19 identity for sum c c feq)
     const R t3 = drho * R(1.0 / 3.0);
     const R rux = rho * ux, ruy = rho * uy;
@@ -461,13 +493,13 @@ __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R
     if (P.has_force) {
         // Guo source (1 - w/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F, times SC
         const R pre = (R(1) - R(0.5) * om) * R(SC);
-        const R uF = fma(ux, P.F[0], fma(uy, P.F[1], uz * P.F[2]));
+        const R uF = fma(ux, Fx, fma(uy, Fy, uz * Fz));
         h[0] = fma(pre * weight<R>(0), R(-3) * uF, h[0]);
 #pragma unroll
         for (int i = 1; i < NQ; i += 2) {
             const V3 c = dirv(i);
             const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
-            const R cF = R(c.x) * P.F[0] + R(c.y) * P.F[1] + R(c.z) * P.F[2];
+            const R cF = R(c.x) * Fx + R(c.y) * Fy + R(c.z) * Fz;
             const R ev = pre * weight<R>(i) * (R(9) * e * cF - R(3) * uF);
             const R od = pre * weight<R>(i) * (R(3) * cF);
             h[i] += ev + od;

@@ -624,18 +624,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_mass_final(const double* partia
 // --------------------------------------------------------------------------
 // Host launchers
 // --------------------------------------------------------------------------
-template <int K>
-static Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
-{
-    using R = typename Codec<K>::real;
-    Phys<R> P;
-    P.tau0 = R(d.tau0);
-    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
-    P.rho0 = R(d.rho0);
-    for (int a = 0; a < 3; a++) P.F[a] = R(d.force[a]);
-    P.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
-    return P;
-}
 
 static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 

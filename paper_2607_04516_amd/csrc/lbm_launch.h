@@ -23,7 +23,26 @@ struct DevCtx {
     const unsigned* adj_list;  // canonical indices of the two-layer face shell (general-path adjoint)
     long long adj_list_n;
     double tau0, c_smag, delta, rho0, force[3];
+    double omega[3];      // rotation vector in lattice units (Coriolis); zero: none
 };
+
+// Collision parameters of a context in the codec's arithmetic type.
+template <int K>
+static inline Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
+{
+    using R = typename Codec<K>::real;
+    Phys<R> P;
+    P.tau0 = R(d.tau0);
+    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
+    P.rho0 = R(d.rho0);
+    for (int a = 0; a < 3; a++) {
+        P.F[a] = R(d.force[a]);
+        P.W2[a] = R(2.0 * d.omega[a]);
+    }
+    P.has_rot = (d.omega[0] != 0.0 || d.omega[1] != 0.0 || d.omega[2] != 0.0) ? 1 : 0;
+    P.has_force = (P.has_rot || d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+    return P;
+}
 
 // Host copy of the odd kernel's test for waves it leaves to the general
 // kernel (k_odd in lbm_step.hip applies the same test).

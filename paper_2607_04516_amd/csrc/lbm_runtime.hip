@@ -187,7 +187,10 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->d.c_smag = params->c_smag;
     c->d.delta = params->delta;
     c->d.rho0 = params->rho0;
-    for (int a = 0; a < 3; a++) c->d.force[a] = params->body_force[a];
+    for (int a = 0; a < 3; a++) {
+        c->d.force[a] = params->body_force[a];
+        c->d.omega[a] = 0.0;
+    }
 
     // bit-packed solid mask, cell counts
     std::vector<uint64_t> bits((size_t)g.wpr * g.ny * g.nz, 0ull);
@@ -345,6 +348,17 @@ int lbm_set_inflow(lbm_ctx* c, int32_t face, const double* u)
     // the host copy must stay valid until the copy ran
     HIPCHK(c, hipStreamSynchronize(c->stream), "upload inflow profile");
     c->prof_set[face] = true;
+    return LBM_OK;
+}
+
+int lbm_set_rotation(lbm_ctx* c, const double* omega)
+{
+    if (!c) return LBM_EINVAL;
+    if (!omega) return fail(c, LBM_EINVAL, "NULL rotation vector");
+    for (int a = 0; a < 3; a++)
+        if (!std::isfinite(omega[a]) || std::fabs(omega[a]) > 0.25)
+            return fail(c, LBM_EINVAL, "rotation component not finite or beyond 0.25 per time step");
+    for (int a = 0; a < 3; a++) c->d.omega[a] = omega[a];
     return LBM_OK;
 }
 

@@ -326,18 +326,6 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     });
 }
 
-template <int K>
-static Phys<typename Codec<K>::real> phys_from(const DevCtx& d)
-{
-    using R = typename Codec<K>::real;
-    Phys<R> P;
-    P.tau0 = R(d.tau0);
-    P.ksmag = R(18.0 * (d.c_smag * d.delta) * (d.c_smag * d.delta));
-    P.rho0 = R(d.rho0);
-    for (int a = 0; a < 3; a++) P.F[a] = R(d.force[a]);
-    P.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
-    return P;
-}
 
 template <int K>
 static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_t s)
@@ -347,7 +335,7 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
-    const Phys<R> P = phys_from<K>(d);
+    const Phys<R> P = phys_of<K>(d);
     auto* f = (typename C::store*)d.f;
     if (!odd) {
         if (stats)
@@ -376,7 +364,7 @@ static hipError_t launch_push_k(const DevCtx& d, const void* src, void* dst, hip
     using C = Codec<K>;
     const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
     hipLaunchKernelGGL((k_push<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
-                       (const typename C::store*)src, (typename C::store*)dst, d.mask, d.g, phys_from<K>(d), nwaves);
+                       (const typename C::store*)src, (typename C::store*)dst, d.mask, d.g, phys_of<K>(d), nwaves);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = launch_push_cells(d, src, dst, s)) != hipSuccess) return e;

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -60,3 +61,21 @@ def test_params_struct_layout_matches_compiler(tmp_path):
                            str(src), "-o", str(exe)])
     out = subprocess.check_output([str(exe)]).decode().split()
     assert [int(v) for v in out] == [0, 32, 56, 80, 88, 96, 100, 128, 136]
+
+
+def test_earth_rotation_vector():
+    """App. E: Omega_ENU = Omega (0, cos phi, sin phi), times dt, in grid axes."""
+    from paper_2607_04516_amd.binding import OMEGA_EARTH, earth_rotation
+    lat, dt = 23.113, 0.01
+    om = earth_rotation(lat, dt)
+    p = np.radians(lat)
+    np.testing.assert_allclose(om, [0.0, OMEGA_EARTH * dt * np.cos(p), OMEGA_EARTH * dt * np.sin(p)], rtol=1e-15)
+    # Coriolis parameter f = 2 Omega sin phi (per time step)
+    assert abs(2 * om[2] - 2 * OMEGA_EARTH * np.sin(p) * dt) <= 1e-22
+    # grid x turned to point north: the horizontal component lies on grid x
+    r = earth_rotation(lat, dt, grid_angle_deg=90.0)
+    np.testing.assert_allclose(r, [om[1], 0.0, om[2]], atol=1e-20)
+    # a small turn (meridian convergence) keeps the magnitude and the vertical part
+    r = earth_rotation(lat, dt, grid_angle_deg=-0.911)
+    assert abs(np.linalg.norm(r) - OMEGA_EARTH * dt) <= 1e-20 and r[2] == om[2]
+    assert r[0] < 0.0    # grid x turned clockwise from east has a southward part
