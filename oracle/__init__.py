@@ -41,7 +41,8 @@ class _Cfg(ctypes.Structure):
                 ("face", ctypes.c_int32 * 6),
                 ("tau0", ctypes.c_double), ("c_smag", ctypes.c_double),
                 ("delta", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("force", ctypes.c_double * 3), ("omega", ctypes.c_double * 3)]
+                ("force", ctypes.c_double * 3), ("omega", ctypes.c_double * 3),
+                ("inflow_field", ctypes.c_void_p)]
 
 
 _lib = None
@@ -131,6 +132,23 @@ class Oracle:
             for face, prof in inflow.items():
                 self.inflow[face] = np.asarray(prof, np.float64).reshape(nz, 3)
         self.lib = _load()
+        self._field = None
+
+    @property
+    def inflow_field(self):
+        """Optional velocity of every inflow cell, [nz, ny, nx, 3] (None: the
+        per-height profiles).  Read only at inflow cells."""
+        return self._field
+
+    @inflow_field.setter
+    def inflow_field(self, v):
+        if v is None:
+            self._field = None
+            self.cfg.inflow_field = None
+            return
+        a = np.ascontiguousarray(v, np.float64).reshape(self.shape + (3,))
+        self._field = a
+        self.cfg.inflow_field = a.ctypes.data
 
     @property
     def n(self):

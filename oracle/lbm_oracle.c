@@ -83,6 +83,8 @@ typedef struct {
     double rho0;    /* reference density of inflow cells */
     double force[3];/* uniform body force per unit volume (Guo scheme) */
     double omega[3];/* Earth rotation vector in lattice units (App. E), ENU frame */
+    const double *inflow_field; /* optional [N][3] velocity of every inflow cell (App. F:
+                                   the boundary velocity array); NULL: per-height profiles */
 } or_cfg;
 
 /* Error state of the last call (0 = fine). */
@@ -224,6 +226,13 @@ static int is_solid(const or_cfg *g, const uint8_t *solid, const int *p)
 /* Inflow velocity of an inflow cell: the profile of its face at its height z. */
 static void inflow_velocity(const or_cfg *g, const double *inflow, int face, const int *p, double *u)
 {
+    if (g->inflow_field) {
+        const double *v = g->inflow_field + 3 * IDX(g, p[0], p[1], p[2]);
+        u[0] = v[0];
+        u[1] = v[1];
+        u[2] = v[2];
+        return;
+    }
     const double *row = inflow + ((int64_t)face * g->nz + p[2]) * 3;
     u[0] = row[0];
     u[1] = row[1];
