@@ -112,6 +112,60 @@ int lbm_set_inflow(lbm_ctx *ctx, int32_t face, const double *u);
  * component not finite or of magnitude above 0.25). */
 int lbm_set_rotation(lbm_ctx *ctx, const double *omega);
 
+/* Synthetic von Karman inflow turbulence (App. F).  Before every step from
+ * time t the boundary velocity of each active cell becomes
+ *   U_i(t) = U_b,i + sigma_i q(x_i, t),
+ *   q_a(x, t) = sum_m A_m,a cos(k_m . x - omega_m t + phi_m,a),
+ * with U_b,i the face's per-height profile (lbm_set_inflow) and x the global
+ * lattice coordinates of the cell (origin + index), so grids that tile one
+ * domain see one field.  Active cells: cells of the INFLOW_EQ faces x-, x+,
+ * y-, y+, z+ (never z-), not solid, on one face each (the lower-numbered
+ * one), optionally only where U_b . n_f > 0 (n_f inward normal); faces whose
+ * mean velocity has characteristic speed |U_f| (or |U_f . n_f|) <= 1e-7 are
+ * dropped.  u_ref = mean |U_b| and e_c = sum U_b / |sum U_b| over the active
+ * cells (e_c = x when the sum vanishes); omega_m = u_ref k_m . e_c, so the
+ * pattern is carried along the mean flow.  Modes: k_m log-stratified in
+ * [2 pi / (10 L), pi] (k_min = 0.1 pi if that band is empty), isotropic
+ * directions, amplitude sqrt(W(k_m)) with W(k) = k^4 / (1 + (k L)^2)^(17/6),
+ * normalised to unit RMS per component, times gain[a].  sigma_i = intensity
+ * times |U_b,i| (or |U_b,i . n_f|) when intensity > 0, else sigma0.  With a
+ * stride s > 1, q is taken at anchors t_a = s floor(t / s), held or
+ * interpolated linearly to t_a + s.  Random draws: U = (splitmix64(seed +
+ * 2^32 (r + 1) + 6 m + j) >> 11) 2^-53 for realization r (the face, or 0
+ * when shared), mode m, draw j: r_m, mu = 2U - 1, theta = 2 pi U, then the
+ * phases of x, y, z, each 2 pi U.  The field is evaluated in double
+ * precision on the device.  Profiles set later rebuild the generator.
+ * p = NULL turns the generator off (boundaries back to the profiles).
+ * While it is on, lbm_push_step and lbm_adjoint_step return ESTATE.
+ * Errors: EINVAL (n_modes outside [1, 4096], stride < 1, length_scale not
+ * positive, a non-finite value), ENOMEM, EHIP. */
+typedef struct {
+    int32_t n_modes;      /* N_m modes per realization */
+    int32_t stride;       /* s >= 1 */
+    int32_t interpolate;  /* with s > 1: 0 hold q(t_a), 1 linear between t_a and t_a + s */
+    int32_t char_normal;  /* 0: characteristic speed |U|, 1: |U . n_f| (faces and sigma_i) */
+    int32_t inflow_only;  /* 1: only cells with U_b . n_f > 0 */
+    int32_t shared;       /* 1: one realization for every face */
+    double length_scale;  /* integral length L, lattice units */
+    double intensity;     /* I; <= 0 selects sigma0 */
+    double sigma0;        /* fluctuation level when intensity <= 0 */
+    double gain[3];       /* component gains g_x, g_y, g_z */
+    double origin[3];     /* global lattice coordinates of cell (0, 0, 0) */
+    uint64_t seed;
+} lbm_turbulence;
+
+int lbm_set_turbulence(lbm_ctx *ctx, const lbm_turbulence *p);
+
+/* The generator's active cell count, u_ref and e_c (zeros when it is off). */
+int lbm_turbulence_info(lbm_ctx *ctx, int64_t *n_active, double *u_ref, double *e_c);
+
+/* Copy the current boundary velocity of one INFLOW_EQ face to host double
+ * out[n2][n1][3] (x faces [nz][ny], y faces [nz][nx], z faces [ny][nx]):
+ * the velocity the inflow cells of that face took in the last step (the
+ * profile, or profile plus synthetic turbulence).  Solid cells hold the
+ * profile value.  Synchronises.  Errors: EINVAL (face not INFLOW_EQ, NULL). */
+int lbm_get_inflow(lbm_ctx *ctx, int32_t face, double *out);
+
 /* Re-initialise the state at t = 0 to feq(rho0, u0[z] + noise) in fluid
  * cells.  u0: host double [nz][3], or NULL for params.u_init. */
 int lbm_reset(lbm_ctx *ctx, const double *u0);

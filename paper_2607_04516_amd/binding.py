@@ -48,7 +48,15 @@ class _Params(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p)]
 
 
-EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_rotation", "lbm_reset", "lbm_step", "lbm_step_probed",
+class _Turbulence(ctypes.Structure):
+    _fields_ = [("n_modes", ctypes.c_int32), ("stride", ctypes.c_int32), ("interpolate", ctypes.c_int32),
+                ("char_normal", ctypes.c_int32), ("inflow_only", ctypes.c_int32), ("shared", ctypes.c_int32),
+                ("length_scale", ctypes.c_double), ("intensity", ctypes.c_double), ("sigma0", ctypes.c_double),
+                ("gain", ctypes.c_double * 3), ("origin", ctypes.c_double * 3), ("seed", ctypes.c_uint64)]
+
+
+EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_rotation", "lbm_set_turbulence",
+           "lbm_turbulence_info", "lbm_get_inflow", "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
            "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read"]
@@ -71,6 +79,9 @@ def load(path: str = LIB_PATH):
         "lbm_destroy": ([P], None),
         "lbm_set_inflow": ([P, I32, P], ctypes.c_int),
         "lbm_set_rotation": ([P, P], ctypes.c_int),
+        "lbm_set_turbulence": ([P, ctypes.POINTER(_Turbulence)], ctypes.c_int),
+        "lbm_turbulence_info": ([P, P, P, P], ctypes.c_int),
+        "lbm_get_inflow": ([P, I32, P], ctypes.c_int),
         "lbm_reset": ([P, P], ctypes.c_int),
         "lbm_step": ([P, I64], ctypes.c_int),
         "lbm_step_probed": ([P, I64, P], ctypes.c_int),
@@ -181,6 +192,38 @@ class LBM:
         """Rotation vector of the frame in lattice units (x, y, z); zero disables Coriolis."""
         om = np.ascontiguousarray(omega, np.float64).reshape(3)
         self._check(self.lib.lbm_set_rotation(self.ctx, om.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_turbulence(self, n_modes=64, length_scale=20.0, intensity=0.1, sigma0=0.0, gains=(1.0, 1.0, 1.0),
+                       char_normal=False, inflow_only=False, shared=False, stride=1, interpolate=False,
+                       seed=0, origin=(0.0, 0.0, 0.0), enable=True):
+        """Synthetic von Karman inflow on the INFLOW_EQ faces (enable=False: off)."""
+        if not enable:
+            self._check(self.lib.lbm_set_turbulence(self.ctx, None))
+            return
+        t = _Turbulence()
+        t.n_modes, t.stride, t.interpolate = int(n_modes), int(stride), int(bool(interpolate))
+        t.char_normal, t.inflow_only, t.shared = int(bool(char_normal)), int(bool(inflow_only)), int(bool(shared))
+        t.length_scale, t.intensity, t.sigma0 = float(length_scale), float(intensity), float(sigma0)
+        for a in range(3):
+            t.gain[a] = float(gains[a])
+            t.origin[a] = float(origin[a])
+        t.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        self._check(self.lib.lbm_set_turbulence(self.ctx, ctypes.byref(t)))
+
+    def turbulence_info(self):
+        n = ctypes.c_int64(0)
+        u = ctypes.c_double(0.0)
+        e = (ctypes.c_double * 3)()
+        self._check(self.lib.lbm_turbulence_info(self.ctx, ctypes.byref(n), ctypes.byref(u), e))
+        return int(n.value), float(u.value), np.array(list(e))
+
+    def get_inflow(self, face):
+        """Current boundary velocities of an INFLOW_EQ face, [n2, n1, 3] float64."""
+        a = int(face) // 2
+        shape = {0: (self.nz, self.ny), 1: (self.nz, self.nx), 2: (self.ny, self.nx)}[a]
+        out = np.zeros(shape + (3,), np.float64)
+        self._check(self.lib.lbm_get_inflow(self.ctx, int(face), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def reset(self, u0=None):
         if u0 is None:

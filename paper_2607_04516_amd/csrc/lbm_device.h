@@ -139,7 +139,28 @@ struct Geo {
     long long S;         // slice stride of the in-place array = pitch*ny*nz
     long long N;         // nx*ny*nz
     long long ghost_off[6];  // element offset of each outflow face's ghost block
+    long long in_off[6];     // first per-cell inflow entry of each INFLOW_EQ face (-1: none)
 };
+
+// Per-cell inflow velocities (the boundary velocity array): three doubles
+// per cell of every INFLOW_EQ face, faces stacked from x- to z+; an x face is
+// indexed y + ny z, a y face x + nx z, a z face x + nx y.
+__host__ __device__ inline long long inflow_slot(const Geo& g, int F, int x, int y, int z)
+{
+    const int a = F >> 1;
+    const long long j = a == 0 ? y + (long long)g.ny * z : a == 1 ? x + (long long)g.nx * z : x + (long long)g.nx * y;
+    return g.in_off[F] + j;
+}
+
+template <typename R>
+__device__ inline void load_inflow(const double* __restrict__ uin, const Geo& g, int F, int x, int y, int z, R& ux,
+                                   R& uy, R& uz)
+{
+    const double* p = uin + 3 * inflow_slot(g, F, x, y, z);
+    ux = R(p[0]);
+    uy = R(p[1]);
+    uz = R(p[2]);
+}
 
 template <typename R>
 struct Phys {
@@ -191,7 +212,7 @@ __device__ inline bool solid_at(const uint64_t* __restrict__ mask, const Geo& g,
 __device__ inline int dimn(const Geo& g, int a) { return a == 0 ? g.nx : (a == 1 ? g.ny : g.nz); }
 
 // Lowest-numbered inflow face whose layer holds (x,y,z), or -1.
-__device__ inline int inflow_face_of(const Geo& g, int x, int y, int z)
+__host__ __device__ inline int inflow_face_of(const Geo& g, int x, int y, int z)
 {
     if (g.face[0] == F_INFLOW && x == 0) return 0;
     if (g.face[1] == F_INFLOW && x == g.nx - 1) return 1;

@@ -32,15 +32,6 @@ __device__ __forceinline__ void static_for(Fn&& fn)
 
 constexpr int MODE_EVEN = 0, MODE_ODD = 1, MODE_PUSH = 2;
 
-template <typename R>
-__device__ inline void load_profile(const double* __restrict__ prof, int nz, int face, int z, R& ux, R& uy, R& uz)
-{
-    const double* p = prof + ((long long)face * nz + z) * 3;
-    ux = R(p[0]);
-    uy = R(p[1]);
-    uz = R(p[2]);
-}
-
 // Wave -> (chunk, y, z) with a block order that keeps consecutive chunks of a
 // row on one XCD (blocks are dealt to the 8 XCDs round robin).
 __device__ inline long long xcd_block(long long nblocks_padded)
@@ -53,7 +44,7 @@ __device__ inline long long xcd_block(long long nblocks_padded)
 // Every boundary rule, per cell: the step of one cell (x, y, z) in any mode.
 template <int K, int MODE, bool STATS>
 __device__ inline void general_cell(typename Codec<K>::store* dst, const typename Codec<K>::store* src,
-                                    const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+                                    const uint64_t* __restrict__ mask, const double* __restrict__ uin,
                                     const typename Codec<K>::store* __restrict__ ghost, const Geo& g, const Lay& ls,
                                     const Lay& ld, const Phys<typename Codec<K>::real>& P,
                                     typename Codec<K>::real* stats, int x, int y, int z)
@@ -76,7 +67,7 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
     const int inf = inflow_face_of(g, x, y, z);
     if (inf >= 0) {
         // inflow cell: post-collision state is feq(rho0, u_in(z)) whatever it held
-        load_profile<R>(prof, g.nz, inf, z, ux, uy, uz);
+        load_inflow<R>(uin, g, inf, x, y, z, ux, uy, uz);
         equilibrium_shifted<R>(P.rho0, R(0), ux, uy, uz, h);
 #pragma unroll
         for (int i = 0; i < NQ; i++) h[i] *= R(C::SC);
@@ -157,7 +148,7 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
 template <int K, int MODE, bool STATS>
 __global__ void __launch_bounds__(256)
 k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
-       const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
+       const double* __restrict__ uin, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
        Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nblocks_padded,
        const unsigned* __restrict__ wlist)
 {
@@ -228,14 +219,14 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
 
     // ---------------- general path: every boundary rule, per lane ----------------
     if (x >= g.nx) return;
-    general_cell<K, MODE, STATS>(dst, src, mask, prof, ghost, g, ls, ld, P, stats, x, y, z);
+    general_cell<K, MODE, STATS>(dst, src, mask, uin, ghost, g, ls, ld, P, stats, x, y, z);
 }
 
 // One cell on the general path, for a list of cells (thread per cell).
 template <int K, int MODE>
 __global__ void __launch_bounds__(256)
 k_cells(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
-        const double* __restrict__ prof, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
+        const double* __restrict__ uin, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
         Phys<typename Codec<K>::real> P, const unsigned* __restrict__ cells, long long ncells)
 {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -243,7 +234,7 @@ k_cells(typename Codec<K>::store* dst, const typename Codec<K>::store* src, cons
     const long long n = cells[t];
     const int x = (int)(n % g.nx);
     const long long row = n / g.nx;
-    general_cell<K, MODE, false>(dst, src, mask, prof, ghost, g, ls, ld, P, (typename Codec<K>::real*)nullptr, x,
+    general_cell<K, MODE, false>(dst, src, mask, uin, ghost, g, ls, ld, P, (typename Codec<K>::real*)nullptr, x,
                                  (int)(row % g.ny), (int)(row / g.ny));
 }
 
@@ -337,7 +328,7 @@ __device__ inline void load_cell(const typename Codec<K>::store* f, const uint64
 // then encoded), 0 in solid cells and padding.
 template <int K>
 __global__ void __launch_bounds__(256)
-k_init(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+k_init(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin,
        const double* __restrict__ u0, Geo g, Lay L, double rho0, double amp, uint64_t seed)
 {
     using C = Codec<K>;
@@ -353,7 +344,7 @@ k_init(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
         double u[3];
         const int inf = inflow_face_of(g, x, y, z);
         if (inf >= 0) {
-            load_profile<double>(prof, g.nz, inf, z, u[0], u[1], u[2]);
+            load_inflow<double>(uin, g, inf, x, y, z, u[0], u[1], u[2]);
         } else {
             const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
             for (int c = 0; c < 3; c++) {
@@ -371,7 +362,7 @@ k_init(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
 // equilibrium, solid cells 0.
 template <int K>
 __global__ void __launch_bounds__(256)
-k_export(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+k_export(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin,
          Geo g, Lay L, Phys<typename Codec<K>::real> P, int phase, typename Codec<K>::store* dst)
 {
     using C = Codec<K>;
@@ -388,7 +379,7 @@ k_export(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, c
         const int inf = inflow_face_of(g, x, y, z);
         if (inf >= 0) {
             R u[3], heq[NQ];
-            load_profile<R>(prof, g.nz, inf, z, u[0], u[1], u[2]);
+            load_inflow<R>(uin, g, inf, x, y, z, u[0], u[1], u[2]);
             equilibrium_shifted<R>(P.rho0, R(0), u[0], u[1], u[2], heq);
             for (int i = 0; i < NQ; i++) v[i] = C::enc(heq[i]);
         } else {
@@ -420,7 +411,7 @@ k_import(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, Geo g, 
 // Macroscopic fields (rho, u, nu_t = (tau_eff - tau0)/3) of the current state.
 template <int K>
 __global__ void __launch_bounds__(256)
-k_macros(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+k_macros(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin,
          Geo g, Lay L, Phys<typename Codec<K>::real> P, int phase, typename Codec<K>::real* rho,
          typename Codec<K>::real* u, typename Codec<K>::real* nut)
 {
@@ -435,7 +426,7 @@ k_macros(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, c
     if (!solid_at(mask, g, x, y, z)) {
         const int inf = inflow_face_of(g, x, y, z);
         if (inf >= 0) {
-            load_profile<R>(prof, g.nz, inf, z, ux, uy, uz);
+            load_inflow<R>(uin, g, inf, x, y, z, ux, uy, uz);
         } else {
             typename C::store v[NQ];
             load_cell<K>(f, mask, g, L, phase, x, y, z, v);
@@ -459,7 +450,7 @@ k_macros(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask, c
 // rho and u of one cell for probes (solid: rho0, 0; inflow: rho0, u_in).
 template <int K>
 __device__ inline void cell_rho_u(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask,
-                                  const double* __restrict__ prof, const Geo& g, const Lay& L,
+                                  const double* __restrict__ uin, const Geo& g, const Lay& L,
                                   const Phys<typename Codec<K>::real>& P, int phase, int x, int y, int z,
                                   typename Codec<K>::real* out)
 {
@@ -470,7 +461,7 @@ __device__ inline void cell_rho_u(const typename Codec<K>::store* f, const uint6
     if (solid_at(mask, g, x, y, z)) return;
     const int inf = inflow_face_of(g, x, y, z);
     if (inf >= 0) {
-        load_profile<R>(prof, g.nz, inf, z, out[1], out[2], out[3]);
+        load_inflow<R>(uin, g, inf, x, y, z, out[1], out[2], out[3]);
         return;
     }
     typename C::store v[NQ];
@@ -484,7 +475,7 @@ __device__ inline void cell_rho_u(const typename Codec<K>::store* f, const uint6
 
 template <int K>
 __global__ void k_probe_points(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask,
-                               const double* __restrict__ prof, Geo g, Lay L, Phys<typename Codec<K>::real> P,
+                               const double* __restrict__ uin, Geo g, Lay L, Phys<typename Codec<K>::real> P,
                                int phase, const float* pts, int np, float* out)
 {
     using R = typename Codec<K>::real;
@@ -512,7 +503,7 @@ __global__ void k_probe_points(const typename Codec<K>::store* f, const uint64_t
         }
         if (w == R(0)) continue;
         R v[4];
-        cell_rho_u<K>(f, mask, prof, g, L, P, phase, q[0], q[1], q[2], v);
+        cell_rho_u<K>(f, mask, uin, g, L, P, phase, q[0], q[1], q[2], v);
         for (int j = 0; j < 4; j++) acc[j] += w * v[j];
     }
     for (int j = 0; j < 4; j++) out[4 * p + j] = float(acc[j]);
@@ -520,14 +511,14 @@ __global__ void k_probe_points(const typename Codec<K>::store* f, const uint64_t
 
 template <int K>
 __global__ void k_probe_cells(const typename Codec<K>::store* f, const uint64_t* __restrict__ mask,
-                              const double* __restrict__ prof, Geo g, Lay L, Phys<typename Codec<K>::real> P,
+                              const double* __restrict__ uin, Geo g, Lay L, Phys<typename Codec<K>::real> P,
                               int phase, const int* cells, int np, typename Codec<K>::real* acc)
 {
     using R = typename Codec<K>::real;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     R v[4];
-    cell_rho_u<K>(f, mask, prof, g, L, P, phase, cells[3 * p], cells[3 * p + 1], cells[3 * p + 2], v);
+    cell_rho_u<K>(f, mask, uin, g, L, P, phase, cells[3 * p], cells[3 * p + 1], cells[3 * p + 2], v);
     acc[3 * p] += v[1];
     acc[3 * p + 1] += v[2];
     acc[3 * p + 2] += v[3];
@@ -635,7 +626,7 @@ static hipError_t step_k(const DevCtx& d, const void* src, void* dst, Lay ls, La
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
     hipLaunchKernelGGL((k_step<K, MODE, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)dst,
-                       (const typename C::store*)src, d.mask, d.prof, (const typename C::store*)d.ghost, d.g, ls, ld,
+                       (const typename C::store*)src, d.mask, d.uin, (const typename C::store*)d.ghost, d.g, ls, ld,
                        phys_of<K>(d), (typename C::real*)stats, nwaves, nbp, (const unsigned*)nullptr);
     return hipGetLastError();
 }
@@ -652,7 +643,7 @@ static hipError_t general_odd_k(const DevCtx& d, void* stats, hipStream_t s)
     const long long nbp = (nb + 7) / 8 * 8;
     const Lay L{d.g.S, d.g.pitch};
     hipLaunchKernelGGL((k_step<K, MODE_ODD, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)d.f,
-                       (const typename C::store*)d.f, d.mask, d.prof, (const typename C::store*)d.ghost, d.g, L, L,
+                       (const typename C::store*)d.f, d.mask, d.uin, (const typename C::store*)d.ghost, d.g, L, L,
                        phys_of<K>(d), (typename C::real*)stats, nwaves, nbp, d.odd_list);
     return hipGetLastError();
 }
@@ -699,7 +690,7 @@ hipError_t launch_push_cells(const DevCtx& d, const void* src, void* dst, hipStr
     if (d.push_list_n == 0) return hipSuccess;
     LBM_DISPATCH(d.codec, {
         hipLaunchKernelGGL((k_cells<K, MODE_PUSH>), dim3(blocks_for(d.push_list_n, 256)), dim3(256), 0, s,
-                           (typename Codec<K>::store*)dst, (const typename Codec<K>::store*)src, d.mask, d.prof,
+                           (typename Codec<K>::store*)dst, (const typename Codec<K>::store*)src, d.mask, d.uin,
                            (const typename Codec<K>::store*)d.ghost, d.g, canonical(d), canonical(d), phys_of<K>(d),
                            d.push_list, d.push_list_n);
         return hipGetLastError();
@@ -747,7 +738,7 @@ hipError_t launch_init(const DevCtx& d, const double* u0_dev, double amp, uint64
     const long long cells = (long long)d.g.pitch * d.g.ny * d.g.nz;
     LBM_DISPATCH(d.codec, {
         hipLaunchKernelGGL((k_init<K>), dim3(blocks_for(cells, 256)), dim3(256), 0, s, (typename Codec<K>::store*)d.f,
-                           d.mask, d.prof, u0_dev, d.g, padded(d), d.rho0, amp, seed);
+                           d.mask, d.uin, u0_dev, d.g, padded(d), d.rho0, amp, seed);
         return hipGetLastError();
     });
 }
@@ -756,7 +747,7 @@ hipError_t launch_export(const DevCtx& d, int phase, void* dst, hipStream_t s)
 {
     LBM_DISPATCH(d.codec, {
         hipLaunchKernelGGL((k_export<K>), dim3(blocks_for(d.g.N, 256)), dim3(256), 0, s,
-                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.uin, d.g, padded(d), phys_of<K>(d), phase,
                            (typename Codec<K>::store*)dst);
         return hipGetLastError();
     });
@@ -777,7 +768,7 @@ hipError_t launch_macros(const DevCtx& d, int phase, void* rho, void* u, void* n
     LBM_DISPATCH(d.codec, {
         using R = typename Codec<K>::real;
         hipLaunchKernelGGL((k_macros<K>), dim3(blocks_for(d.g.N, 256)), dim3(256), 0, s,
-                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.uin, d.g, padded(d), phys_of<K>(d), phase,
                            (R*)rho, (R*)u, (R*)nut);
         return hipGetLastError();
     });
@@ -787,7 +778,7 @@ hipError_t launch_probe_points(const DevCtx& d, int phase, const float* pts, int
 {
     LBM_DISPATCH(d.codec, {
         hipLaunchKernelGGL((k_probe_points<K>), dim3(blocks_for(np, 64)), dim3(64), 0, s,
-                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.uin, d.g, padded(d), phys_of<K>(d), phase,
                            pts, np, out);
         return hipGetLastError();
     });
@@ -798,7 +789,7 @@ hipError_t launch_probe_cells(const DevCtx& d, int phase, const int* cells, int 
     LBM_DISPATCH(d.codec, {
         using R = typename Codec<K>::real;
         hipLaunchKernelGGL((k_probe_cells<K>), dim3(blocks_for(np, 64)), dim3(64), 0, s,
-                           (const typename Codec<K>::store*)d.f, d.mask, d.prof, d.g, padded(d), phys_of<K>(d), phase,
+                           (const typename Codec<K>::store*)d.f, d.mask, d.uin, d.g, padded(d), phys_of<K>(d), phase,
                            cells, np, (R*)acc);
         return hipGetLastError();
     });

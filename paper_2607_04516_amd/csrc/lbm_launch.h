@@ -15,7 +15,8 @@ struct DevCtx {
     void* f;              // in-place population array [19][nz][ny][pitch]
     const uint64_t* mask; // solid bits [nz][ny][wpr]
     void* ghost;          // outflow ghost entries
-    const double* prof;   // inflow profiles [6][nz][3]
+    const double* prof;   // inflow profiles [6][nz][3] (the per-height base velocities)
+    const double* uin;    // per-cell inflow velocities (inflow_slot); what the step kernels read
     const unsigned* odd_list;  // waves of the odd step left to the general kernel
     long long odd_list_n;
     const unsigned* push_list; // canonical indices of the face layer (general-path push)

@@ -3,6 +3,7 @@
 // update, error reporting.  Declarations and contracts are in include/lbm.h.
 #include "lbm.h"
 #include "lbm_launch.h"
+#include "lbm_turbulence.h"
 
 #include <hip/hip_runtime.h>
 
@@ -29,6 +30,11 @@ struct lbm_ctx {
     void* ghost = nullptr;
     double* prof = nullptr; // device [6][nz][3]
     std::vector<double> prof_host;
+    double* uin = nullptr;  // device per-cell inflow velocities [n_in][3] (inflow_slot)
+    long long n_in = 0;
+    std::vector<uint64_t> bits_host;  // solid bits, kept for the turbulence generator
+    VkGen* vk = nullptr;              // synthetic inflow generator, NULL when off
+    lbm_turbulence vkp{};
     bool prof_set[6] = {false, false, false, false, false, false};
     double* u0 = nullptr;   // device [nz][3] scratch for initialisation
     int* probes = nullptr;  // device [np][3]
@@ -92,8 +98,10 @@ static void free_all(lbm_ctx* c)
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->ev_used = 0;
+    vk_destroy(c->vk);
+    c->vk = nullptr;
     void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
-                    c->push_list, c->adj_list};
+                    c->push_list, c->adj_list, c->uin};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -107,6 +115,7 @@ static void free_all(lbm_ctx* c)
     c->odd_list = nullptr;
     c->push_list = nullptr;
     c->adj_list = nullptr;
+    c->uin = nullptr;
 }
 
 static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
@@ -182,6 +191,13 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         g.ghost_off[F] = goff;
         if (g.face[F] == LBM_OUTFLOW_ZG) goff += 5 * face_cells_host(g, F);
     }
+    for (int F = 0; F < 6; F++) {
+        g.in_off[F] = -1;
+        if (g.face[F] == LBM_INFLOW_EQ) {
+            g.in_off[F] = c->n_in;
+            c->n_in += face_cells_host(g, F);
+        }
+    }
     c->d.codec = params->storage;
     c->d.tau0 = params->tau0;
     c->d.c_smag = params->c_smag;
@@ -218,6 +234,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         (rc = device_alloc(c, &c->ghost, (size_t)goff * c->store_bytes, "ghost planes")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->prof, 18 * (size_t)g.nz * sizeof(double), "profiles")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->u0, 3 * (size_t)g.nz * sizeof(double), "u0")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->uin, 3 * (size_t)c->n_in * sizeof(double), "inflow velocities")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->red_partial, 5 * (size_t)mass_blocks(g) * sizeof(double), "reduction")) !=
             LBM_OK ||
         (rc = device_alloc(c, (void**)&c->red_out, 8 * sizeof(double), "reduction")) != LBM_OK) {
@@ -279,6 +296,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->prof_host.assign(18 * (size_t)g.nz, 0.0);
     hipError_t e = hipMemcpy(c->mask, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->prof, 0, 18 * (size_t)g.nz * sizeof(double));
+    if (e == hipSuccess && c->n_in) e = hipMemset(c->uin, 0, 3 * (size_t)c->n_in * sizeof(double));
     if (e == hipSuccess) e = hipMemset(c->f, 0, pop_bytes);
     if (e == hipSuccess && goff) e = hipMemset(c->ghost, 0, (size_t)goff * c->store_bytes);
     if (e != hipSuccess) {
@@ -291,6 +309,8 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->d.mask = c->mask;
     c->d.ghost = c->ghost;
     c->d.prof = c->prof;
+    c->d.uin = c->uin;
+    c->bits_host = std::move(bits);
     if ((rc = lbm_reset(c, nullptr)) != LBM_OK) {
         g_create_error = c->err;
         free_all(c);
@@ -332,6 +352,26 @@ int lbm_set_stream(lbm_ctx* c, void* s)
     return LBM_OK;
 }
 
+// Fill the per-cell inflow velocities of one face from its height profile.
+static int broadcast_profile(lbm_ctx* c, int F)
+{
+    const Geo& g = c->d.g;
+    if (g.in_off[F] < 0) return LBM_OK;
+    const long long area = face_cells_host(g, F);
+    const int a = F >> 1;
+    const long long n1 = a == 0 ? g.ny : g.nx;
+    std::vector<double> h(3 * (size_t)area);
+    for (long long j = 0; j < area; j++) {
+        const long long j2 = j / n1;   // z for x and y faces, y for z faces
+        const int z = a == 2 ? (F & 1 ? g.nz - 1 : 0) : (int)j2;
+        for (int k = 0; k < 3; k++) h[3 * j + k] = c->prof_host[((size_t)F * g.nz + z) * 3 + k];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->uin + 3 * g.in_off[F], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream), "upload inflow velocities");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "upload inflow velocities");
+    return LBM_OK;
+}
+
 int lbm_set_inflow(lbm_ctx* c, int32_t face, const double* u)
 {
     if (!c) return LBM_EINVAL;
@@ -348,6 +388,16 @@ int lbm_set_inflow(lbm_ctx* c, int32_t face, const double* u)
     // the host copy must stay valid until the copy ran
     HIPCHK(c, hipStreamSynchronize(c->stream), "upload inflow profile");
     c->prof_set[face] = true;
+    int rc = broadcast_profile(c, face);
+    if (rc != LBM_OK) return rc;
+    if (c->vk) {   // the generator's mean field, sigma and u_ref follow the profiles
+        VkGen* v = nullptr;
+        std::string err;
+        rc = vk_create(&v, c->vkp, c->d.g, c->bits_host, c->prof_host, err);
+        if (rc != LBM_OK) return fail(c, rc, err);
+        vk_destroy(c->vk);
+        c->vk = v;
+    }
     return LBM_OK;
 }
 
@@ -362,11 +412,54 @@ int lbm_set_rotation(lbm_ctx* c, const double* omega)
     return LBM_OK;
 }
 
+int lbm_set_turbulence(lbm_ctx* c, const lbm_turbulence* p)
+{
+    if (!c) return LBM_EINVAL;
+    VkGen* v = nullptr;
+    if (p) {
+        std::string err;
+        int rc = vk_create(&v, *p, c->d.g, c->bits_host, c->prof_host, err);
+        if (rc != LBM_OK) return fail(c, rc, err);
+    }
+    // back to the profiles everywhere; the generator writes its cells at the next step
+    for (int F = 0; F < 6; F++) {
+        int rc = broadcast_profile(c, F);
+        if (rc != LBM_OK) {
+            vk_destroy(v);
+            return rc;
+        }
+    }
+    vk_destroy(c->vk);
+    c->vk = v;
+    if (p) c->vkp = *p;
+    return LBM_OK;
+}
+
+int lbm_turbulence_info(lbm_ctx* c, int64_t* n_active, double* u_ref, double* e_c)
+{
+    if (!c) return LBM_EINVAL;
+    vk_info(c->vk, n_active, u_ref, e_c);
+    return LBM_OK;
+}
+
+int lbm_get_inflow(lbm_ctx* c, int32_t face, double* out)
+{
+    if (!c) return LBM_EINVAL;
+    if (face < 0 || face > 5 || !out || c->d.g.in_off[face] < 0)
+        return fail(c, LBM_EINVAL, "face is not an INFLOW_EQ face, or NULL output");
+    const long long area = face_cells_host(c->d.g, face);
+    HIPCHK(c, hipMemcpyAsync(out, c->uin + 3 * c->d.g.in_off[face], 3 * (size_t)area * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream), "copy inflow velocities");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "copy inflow velocities");
+    return LBM_OK;
+}
+
 int lbm_reset(lbm_ctx* c, const double* u0)
 {
     if (!c) return LBM_EINVAL;
     int rc = upload_u0(c, u0);
     if (rc != LBM_OK) return rc;
+    HIPCHK(c, vk_apply(c->vk, c->uin, 0, c->stream), "synthetic inflow");
     HIPCHK(c, launch_init(c->d, c->u0, c->p.noise_amp, c->p.noise_seed, c->stream), "init kernel");
     c->phase = 0;
     c->t = 0;
@@ -405,6 +498,7 @@ static int one_step(lbm_ctx* c)
     void* st = nullptr;
     int rc;
     if (c->stats && c->stats_stride > 0 && (c->t % c->stats_stride) == 0) st = c->stats;
+    HIPCHK(c, vk_apply(c->vk, c->uin, c->t, c->stream), "synthetic inflow");
     if (c->phase == 0) {
         if ((rc = mark(c)) != LBM_OK) return rc;
         HIPCHK(c, launch_step(c->d, 0, st, c->stream), "even step");
@@ -577,6 +671,7 @@ int lbm_push_step(lbm_ctx* c, const void* src, void* dst)
 {
     if (!c) return LBM_EINVAL;
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct device arrays");
+    if (c->vk) return fail(c, LBM_ESTATE, "push step with synthetic inflow turbulence on");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
     HIPCHK(c, launch_push(c->d, src, dst, c->stream), "push step");
@@ -595,6 +690,7 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
             return fail(c, LBM_EINVAL, "grid too large for the adjoint (an adjoint slice must stay below 2 GiB)");
     }
     if (probe_src && c->np == 0) return fail(c, LBM_ESTATE, "probe source without registered probes");
+    if (c->vk) return fail(c, LBM_ESTATE, "adjoint step with synthetic inflow turbulence on");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
     HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, c->probes, c->np, probe_src, g_inflow, c->stream),

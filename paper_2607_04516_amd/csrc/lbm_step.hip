@@ -58,10 +58,10 @@ __device__ inline void st_pop(T* p, T v)
 }
 
 template <typename R>
-__device__ inline void inflow_eq_stored(const double* __restrict__ prof, const Geo& g, int face, int z, R rho0, R sc,
-                                        R* h)
+__device__ inline void inflow_eq_stored(const double* __restrict__ uin, const Geo& g, int face, int x, int y, int z,
+                                        R rho0, R sc, R* h)
 {
-    const double* p = prof + ((long long)face * g.nz + z) * 3;
+    const double* p = uin + 3 * inflow_slot(g, face, x, y, z);
     equilibrium_shifted<R>(rho0, R(0), R(p[0]), R(p[1]), R(p[2]), h);
 #pragma unroll
     for (int i = 0; i < NQ; i++) h[i] *= sc;
@@ -82,7 +82,7 @@ __device__ inline void add_stats(R* stats, const Geo& g, int x, int y, int z, R 
 // ---------------------------------------------------------------- even step
 template <int K, bool STATS>
 __global__ void __launch_bounds__(256)
-k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof, Geo g,
+k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin, Geo g,
        Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nbp)
 {
     using C = Codec<K>;
@@ -104,9 +104,9 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
     R h[NQ];
     const int inf = inflow_face_of(g, x, y, z);
     if (inf >= 0) {
-        inflow_eq_stored<R>(prof, g, inf, z, P.rho0, R(C::SC), h);
+        inflow_eq_stored<R>(uin, g, inf, x, y, z, P.rho0, R(C::SC), h);
         if constexpr (STATS) {
-            const double* p = prof + ((long long)inf * g.nz + z) * 3;
+            const double* p = uin + 3 * inflow_slot(g, inf, x, y, z);
             add_stats<R>(stats, g, x, y, z, R(p[0]), R(p[1]), R(p[2]));
         }
         sfor<0, NQ>([&](auto ic) {
@@ -138,7 +138,7 @@ __device__ inline bool odd_general_wave(const Geo& g, int cx, int y, int z)
 // ---------------------------------------------------------------- odd step
 template <int K, bool STATS>
 __global__ void __launch_bounds__(256)
-k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin,
       const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P,
       typename Codec<K>::real* stats, long long nwaves, long long nbp)
 {
@@ -236,8 +236,8 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
     }
     R ux, uy, uz;
     if (inflow_lane) {
-        inflow_eq_stored<R>(prof, g, 0, z, P.rho0, R(C::SC), h);
-        const double* p = prof + (long long)z * 3;
+        inflow_eq_stored<R>(uin, g, 0, 0, y, z, P.rho0, R(C::SC), h);
+        const double* p = uin + 3 * inflow_slot(g, 0, 0, y, z);
         ux = R(p[0]);
         uy = R(p[1]);
         uz = R(p[2]);
@@ -339,19 +339,19 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     auto* f = (typename C::store*)d.f;
     if (!odd) {
         if (stats)
-            hipLaunchKernelGGL((k_even<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, d.g, P,
+            hipLaunchKernelGGL((k_even<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P,
                                (R*)stats, nwaves, nbp);
         else
-            hipLaunchKernelGGL((k_even<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, d.g, P,
+            hipLaunchKernelGGL((k_even<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P,
                                (R*)stats, nwaves, nbp);
         return hipGetLastError();
     }
     const auto* gh = (const typename C::store*)d.ghost;
     if (stats)
-        hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, gh, d.g, P,
+        hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, gh, d.g, P,
                            (R*)stats, nwaves, nbp);
     else
-        hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.prof, gh, d.g, P,
+        hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, gh, d.g, P,
                            (R*)stats, nwaves, nbp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -63,6 +63,25 @@ def test_params_struct_layout_matches_compiler(tmp_path):
     assert [int(v) for v in out] == [0, 32, 56, 80, 88, 96, 100, 128, 136]
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbm.so not built")
+def test_turbulence_struct_layout_matches_compiler(tmp_path):
+    import subprocess
+    from paper_2607_04516_amd import binding
+    T = binding._Turbulence
+    src = tmp_path / "tu.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\nint main(void){'
+                   'printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(lbm_turbulence,shared),'
+                   'offsetof(lbm_turbulence,length_scale), offsetof(lbm_turbulence,sigma0),'
+                   'offsetof(lbm_turbulence,gain), offsetof(lbm_turbulence,origin), offsetof(lbm_turbulence,seed),'
+                   'sizeof(lbm_turbulence)); return 0;}\n')
+    exe = tmp_path / "tu"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           str(src), "-o", str(exe)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).decode().split()]
+    assert out == [T.shared.offset, T.length_scale.offset, T.sigma0.offset, T.gain.offset, T.origin.offset,
+                   T.seed.offset, ctypes.sizeof(T)]
+
+
 def test_earth_rotation_vector():
     """App. E: Omega_ENU = Omega (0, cos phi, sin phi), times dt, in grid axes."""
     from paper_2607_04516_amd.binding import OMEGA_EARTH, earth_rotation
