@@ -42,7 +42,8 @@ class _Cfg(ctypes.Structure):
                 ("tau0", ctypes.c_double), ("c_smag", ctypes.c_double),
                 ("delta", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("omega", ctypes.c_double * 3),
-                ("inflow_field", ctypes.c_void_p)]
+                ("inflow_field", ctypes.c_void_p), ("sponge_strength", ctypes.c_double),
+                ("sponge_width", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,6 +77,7 @@ def _load():
         lib.or_adjoint_step.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, P, P]
         lib.or_adjoint_step.restype = ctypes.c_int
         lib.or_step_cell.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        lib.or_collide_cell.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
         lib.or_step_cell.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -115,7 +117,7 @@ class Oracle:
     """One configured oracle lattice (geometry, faces, collision parameters)."""
 
     def __init__(self, nx, ny, nz, faces, tau0, c_smag=0.0, delta=1.0, rho0=1.0,
-                 force=(0.0, 0.0, 0.0), solid=None, inflow=None, omega=(0.0, 0.0, 0.0)):
+                 force=(0.0, 0.0, 0.0), solid=None, inflow=None, omega=(0.0, 0.0, 0.0), sponge=(0, 0.0)):
         self.shape = (nz, ny, nx)
         self.cfg = _Cfg()
         self.cfg.nx, self.cfg.ny, self.cfg.nz = nx, ny, nz
@@ -125,6 +127,7 @@ class Oracle:
         for a in range(3):
             self.cfg.force[a] = float(force[a])
             self.cfg.omega[a] = float(omega[a])
+        self.cfg.sponge_width, self.cfg.sponge_strength = int(sponge[0]), float(sponge[1])
         self.solid = np.zeros(self.shape, np.uint8) if solid is None else \
             np.ascontiguousarray(solid, np.uint8).reshape(self.shape)
         self.inflow = np.zeros((6, nz, 3), np.float64)
@@ -208,6 +211,15 @@ class Oracle:
         u = np.zeros(3)
         tau = self.lib.or_collide(ctypes.byref(self.cfg), _p(fcell), _p(out), _p(rho), _p(u))
         return out, float(rho[0]), u, tau
+
+    def collide_cell(self, fcell, x, y, z):
+        """Post-collision populations of one interior cell at (x, y, z),
+        including the sponge / buffer nudging there."""
+        fcell = np.ascontiguousarray(fcell, np.float64)
+        out = np.zeros(NQ)
+        self.lib.or_collide_cell(ctypes.byref(self.cfg), _p(self.inflow), _p(fcell), int(x), int(y), int(z),
+                                 _p(out))
+        return out
 
     def moments(self, fcell):
         fcell = np.ascontiguousarray(fcell, np.float64)

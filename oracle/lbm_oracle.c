@@ -85,6 +85,9 @@ typedef struct {
     double omega[3];/* Earth rotation vector in lattice units (App. E), ENU frame */
     const double *inflow_field; /* optional [N][3] velocity of every inflow cell (App. F:
                                    the boundary velocity array); NULL: per-height profiles */
+    double sponge_strength;     /* s_max of the sponge / buffer nudging (Sec. 2.2); 0: off */
+    int32_t sponge_width;       /* W, layers next to each nudged face */
+    int32_t pad_;
 } or_cfg;
 
 /* Error state of the last call (0 = fine). */
@@ -362,6 +365,52 @@ int or_init(const or_cfg *g, const uint8_t *solid, const double *inflow, const d
     return 0;
 }
 
+/* Sponge and buffer nudging (Sec. 2.2; widths and rates are not printed, so
+ * these are readings): next to every INFLOW_EQ face except the ground, a cell
+ * at distance d = 1..W from the face layer has strength
+ * s = s_max ((W + 1 - d) / W)^2; near several faces the largest strength
+ * wins (lower-numbered face on ties).  Returns s and the face. */
+static double sponge_at(const or_cfg *g, const int *p, int *face)
+{
+    static const int nudged[5] = {0, 1, 2, 3, 5};
+    int dist[6] = {p[0], g->nx - 1 - p[0], p[1], g->ny - 1 - p[1], p[2], g->nz - 1 - p[2]};
+    double best = 0.0;
+    *face = -1;
+    if (g->sponge_width <= 0 || !(g->sponge_strength > 0.0)) return 0.0;
+    for (int k = 0; k < 5; k++) {
+        int f = nudged[k];
+        if (g->face[f] != OR_INFLOW_EQ) continue;
+        int d = dist[f];
+        if (d < 1 || d > g->sponge_width) continue;
+        double r = (double)(g->sponge_width + 1 - d) / g->sponge_width;
+        double sv = g->sponge_strength * r * r;
+        if (sv > best) {
+            best = sv;
+            *face = f;
+        }
+    }
+    return best;
+}
+
+/* Post-collision populations of one non-solid, non-inflow cell: the
+ * collision, then the nudging toward the equilibrium of the face's target
+ * velocity at the cell's density, f* += s (feq(rho, u_t) - feq(rho, u)),
+ * with u_t the face's profile at the cell's height (the top row for z+). */
+void or_collide_cell(const or_cfg *g, const double *inflow, const double *fc, int x, int y, int z, double *fo)
+{
+    double rho, u[3];
+    or_collide(g, fc, fo, &rho, u);
+    int p[3] = {x, y, z}, face;
+    double s = sponge_at(g, p, &face);
+    if (s > 0.0) {
+        const double *ut = inflow + ((int64_t)face * g->nz + (face == 5 ? g->nz - 1 : z)) * 3;
+        double et[NQ], e[NQ];
+        or_equilibrium(rho, ut, et);
+        or_equilibrium(rho, u, e);
+        for (int i = 0; i < NQ; i++) fo[i] += s * (et[i] - e[i]);
+    }
+}
+
 /* One step.  f: state at t; fnext: state at t+1; fs: work array [19][N]. */
 int or_step(const or_cfg *g, const uint8_t *solid, const double *inflow,
             const double *f, double *fnext, double *fs)
@@ -387,7 +436,7 @@ int or_step(const or_cfg *g, const uint8_t *solid, const double *inflow,
                     or_equilibrium(g->rho0, u, fo);
                 } else {
                     for (int i = 0; i < NQ; i++) fc[i] = f[i * N + n];
-                    or_collide(g, fc, fo, NULL, NULL);
+                    or_collide_cell(g, inflow, fc, x, y, z, fo);
                 }
                 for (int i = 0; i < NQ; i++) fs[i * N + n] = fo[i];
             }
@@ -587,6 +636,7 @@ int or_adjoint_step(const or_cfg *g, const uint8_t *solid, const double *inflow,
 {
     g_err = check_cfg(g);
     if (g_err) return g_err;
+    if (g->sponge_width > 0 && g->sponge_strength > 0.0) return g_err = 6; /* not differentiated */
     int64_t N = (int64_t)g->nx * g->ny * g->nz;
     double *lam_star = work;
     for (int64_t k = 0; k < NQ * N; k++) lam_star[k] = 0.0;
@@ -699,7 +749,7 @@ int or_step_cell(const or_cfg *g, const uint8_t *solid, const double *inflow, co
             double fc[NQ];
             for (int m = 0; m < NQ; m++)
                 fc[m] = win[(((int64_t)m * 5 + (d[2] + 2)) * 5 + (d[1] + 2)) * 5 + (d[0] + 2)];
-            or_collide(g, fc, fo, NULL, NULL);
+            or_collide_cell(g, inflow, fc, s[0], s[1], s[2], fo);
         }
         out[i] = fo[j];
     }

@@ -141,6 +141,7 @@ class Workload:
     probes: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
     heights: np.ndarray | None = None
     omega: tuple = (0.0, 0.0, 0.0)   # Earth rotation vector in lattice units (grid frame)
+    sponge: tuple = (0, 0.0)         # (width W, strength s_max) of the sponge / buffer nudging
 
     @property
     def cells(self):

@@ -11,7 +11,7 @@ FACE_NUM = {"periodic": oracle.PERIODIC, "inflow": oracle.INFLOW_EQ, "outflow": 
 def oracle_for(w: workloads.Workload):
     faces = [FACE_NUM[f] if isinstance(f, str) else int(f) for f in w.faces]
     o = oracle.Oracle(w.nx, w.ny, w.nz, faces, tau0=w.tau0, c_smag=w.c_smag, delta=w.delta,
-                      force=w.force, solid=w.solid, inflow=w.inflow, omega=w.omega)
+                      force=w.force, solid=w.solid, inflow=w.inflow, omega=w.omega, sponge=w.sponge)
     return o
 
 
