@@ -156,6 +156,40 @@ typedef struct {
 
 int lbm_set_turbulence(lbm_ctx *ctx, const lbm_turbulence *p);
 
+/* Sponge and buffer nudging (Sec. 2.2: relaxation layers next to the top and
+ * lateral open faces, toward the target boundary state).  Next to every
+ * INFLOW_EQ face except z-, a fluid cell at distance d = 1..width from the
+ * face layer gets s = strength ((width + 1 - d) / width)^2 (the largest over
+ * the faces, the lower-numbered face on ties), and after its collision
+ *   f*_i += s (feq_i(rho, u_t) - feq_i(rho, u)),
+ * with rho, u the cell's collision moments and u_t the face's profile at the
+ * cell's height (the z+ face: its single row).  Mass is unchanged; the
+ * momentum relaxes by s rho (u_t - u).  Widths and strengths are not printed
+ * in the paper; the ramp is this library's choice.  width 0 or strength 0
+ * turns it off.  While it is on, lbm_adjoint_step returns ESTATE.
+ * Errors: EINVAL (width outside [0, min(nx, ny, nz) - 2], strength outside
+ * [0, 1]). */
+int lbm_set_sponge(lbm_ctx *ctx, int32_t width, double strength);
+
+/* Global flux balancing over the INFLOW_EQ faces (Sec. 2.2 and 2.3: mass-flux
+ * consistency of the boundary data).  Over the non-solid cells of those
+ * faces (each on its owning face) the net outward volume flux is
+ * Phi = sum_i U_i . n_i; the least-squares smallest change of the normal
+ * velocities that zeroes it is U_i -= (Phi / N) n_i for every cell.
+ *   mode 1: apply it to the per-height profiles now (host, double); the
+ *           synthetic-turbulence generator is rebuilt on the new profiles;
+ *   mode 2: apply it to the whole per-cell boundary field (profiles plus
+ *           synthetic turbulence) now and on the device before every step;
+ *   mode 0: stop the per-step balancing.
+ * phi_before, phi_after (host, may be NULL): the net flux before and after
+ * this call's correction (mode 0: the current field's, twice).
+ * Errors: EINVAL (mode), ENOMEM, EHIP. */
+int lbm_balance_flux(lbm_ctx *ctx, int32_t mode, double *phi_before, double *phi_after);
+
+/* Net outward flux of the current per-cell boundary field (device sum in a
+ * fixed order, deterministic).  Synchronises. */
+int lbm_net_flux(lbm_ctx *ctx, double *phi);
+
 /* The generator's active cell count, u_ref and e_c (zeros when it is off). */
 int lbm_turbulence_info(lbm_ctx *ctx, int64_t *n_active, double *u_ref, double *e_c);
 

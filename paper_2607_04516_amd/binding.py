@@ -56,7 +56,8 @@ class _Turbulence(ctypes.Structure):
 
 
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_rotation", "lbm_set_turbulence",
-           "lbm_turbulence_info", "lbm_get_inflow", "lbm_reset", "lbm_step", "lbm_step_probed",
+           "lbm_turbulence_info", "lbm_get_inflow", "lbm_set_sponge", "lbm_balance_flux", "lbm_net_flux",
+           "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
            "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read"]
@@ -82,6 +83,9 @@ def load(path: str = LIB_PATH):
         "lbm_set_turbulence": ([P, ctypes.POINTER(_Turbulence)], ctypes.c_int),
         "lbm_turbulence_info": ([P, P, P, P], ctypes.c_int),
         "lbm_get_inflow": ([P, I32, P], ctypes.c_int),
+        "lbm_set_sponge": ([P, I32, ctypes.c_double], ctypes.c_int),
+        "lbm_balance_flux": ([P, I32, P, P], ctypes.c_int),
+        "lbm_net_flux": ([P, P], ctypes.c_int),
         "lbm_reset": ([P, P], ctypes.c_int),
         "lbm_step": ([P, I64], ctypes.c_int),
         "lbm_step_probed": ([P, I64, P], ctypes.c_int),
@@ -225,6 +229,22 @@ class LBM:
         self._check(self.lib.lbm_get_inflow(self.ctx, int(face), out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    def set_sponge(self, width, strength):
+        """Sponge / buffer nudging next to the INFLOW_EQ faces (width 0: off)."""
+        self._check(self.lib.lbm_set_sponge(self.ctx, int(width), float(strength)))
+
+    def balance_flux(self, mode):
+        """Global flux balancing: 1 profiles now, 2 the full field every step, 0 off.
+        Returns (phi_before, phi_after)."""
+        a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(self.lib.lbm_balance_flux(self.ctx, int(mode), ctypes.byref(a), ctypes.byref(b)))
+        return float(a.value), float(b.value)
+
+    def net_flux(self):
+        v = ctypes.c_double(0.0)
+        self._check(self.lib.lbm_net_flux(self.ctx, ctypes.byref(v)))
+        return float(v.value)
+
     def reset(self, u0=None):
         if u0 is None:
             self._check(self.lib.lbm_reset(self.ctx, None))
@@ -328,6 +348,8 @@ def from_workload(w, storage=None, **kw):
         lat.set_inflow(face, prof)
     if any(float(v) != 0.0 for v in w.omega):
         lat.set_rotation(w.omega)
+    if w.sponge[0] > 0 and w.sponge[1] > 0.0:
+        lat.set_sponge(*w.sponge)
     lat.reset(w.u0)
     return lat
 

@@ -397,41 +397,70 @@ k_adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next, const uin
     }
 }
 
-// Probe sources: lam(x_p) += src_p . (M c_j - u)/rho, probes in order (one
-// thread, so repeated cells add deterministically); M = I without rotation,
-// M c = c - Omega x c with it (the Coriolis part of F/2 in u).
+// Probe sources: lam(x_p) += src_p . (M c_j - u)/rho for the registered
+// probes; M = I without rotation, M c = c - Omega x c with it (the Coriolis
+// part of F/2 in u).  One block: each thread forms the 19 contributions of
+// one probe into LDS; then the first probe of every cell adds, in probe
+// order, the contributions of all probes of that cell and updates lam once,
+// so repeated cells are handled without races and the result does not
+// depend on scheduling.  Probes are taken 256 at a time.
+constexpr int PROBE_CHUNK = 256;
+
 template <int K>
-__global__ void k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_t, typename Codec<K>::real* lam,
-                                 const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P,
-                                 const int* probes, int np, const typename Codec<K>::real* src)
+__global__ void __launch_bounds__(PROBE_CHUNK)
+k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_t, typename Codec<K>::real* lam,
+                 const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P, const int* probes, int np,
+                 const typename Codec<K>::real* src)
 {
     using C = Codec<K>;
     using R = typename C::real;
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int p = 0; p < np; p++) {
-        const int x = probes[3 * p], y = probes[3 * p + 1], z = probes[3 * p + 2];
-        if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) >= 0) continue;
-        const long long n = cidx(g, x, y, z);
-        R h[NQ];
-        for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
-        R drho, ux, uy, uz;
-        moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
-        const R inv_rho = fast_rcp<R>(P.rho0 + drho);
-        R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
-        const R su = sx * ux + sy * uy + sz * uz;
-        if (P.has_rot) {   // src . (M c) = (M^T src) . c, M^T s = s + (W2 x s)/2
-            const R* W2 = P.W2;
-            const R ax = sx + R(0.5) * (W2[1] * sz - W2[2] * sy);
-            const R ay = sy + R(0.5) * (W2[2] * sx - W2[0] * sz);
-            const R az = sz + R(0.5) * (W2[0] * sy - W2[1] * sx);
-            sx = ax;
-            sy = ay;
-            sz = az;
+    __shared__ long long cell[PROBE_CHUNK];
+    __shared__ R con[PROBE_CHUNK][NQ];
+    const int t = threadIdx.x;
+    for (int base = 0; base < np; base += PROBE_CHUNK) {
+        const int p = base + t;
+        const int cnt = min(PROBE_CHUNK, np - base);
+        long long n = -1;
+        if (p < np) {
+            const int x = probes[3 * p], y = probes[3 * p + 1], z = probes[3 * p + 2];
+            if (!solid_at(mask, g, x, y, z) && inflow_face_of(g, x, y, z) < 0) {
+                n = cidx(g, x, y, z);
+                R h[NQ];
+                for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
+                R drho, ux, uy, uz;
+                moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
+                const R inv_rho = fast_rcp<R>(P.rho0 + drho);
+                R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
+                const R su = sx * ux + sy * uy + sz * uz;
+                if (P.has_rot) {   // src . (M c) = (M^T src) . c, M^T s = s + (W2 x s)/2
+                    const R* W2 = P.W2;
+                    const R ax = sx + R(0.5) * (W2[1] * sz - W2[2] * sy);
+                    const R ay = sy + R(0.5) * (W2[2] * sx - W2[0] * sz);
+                    const R az = sz + R(0.5) * (W2[0] * sy - W2[1] * sx);
+                    sx = ax;
+                    sy = ay;
+                    sz = az;
+                }
+                for (int j = 0; j < NQ; j++) {
+                    const V3 c = dirv(j);
+                    con[t][j] = (R(c.x) * sx + R(c.y) * sy + R(c.z) * sz - su) * inv_rho;
+                }
+            }
         }
-        for (int j = 0; j < NQ; j++) {
-            const V3 c = dirv(j);
-            lam[(long long)j * g.N + n] += (R(c.x) * sx + R(c.y) * sy + R(c.z) * sz - su) * inv_rho;
+        cell[t] = n;
+        __syncthreads();
+        bool first = n >= 0;
+        for (int u = 0; u < t && first; u++) first = cell[u] != n;
+        if (first) {
+            R acc[NQ];
+            for (int j = 0; j < NQ; j++) acc[j] = con[t][j];
+            for (int u = t + 1; u < cnt; u++)
+                if (cell[u] == n)
+                    for (int j = 0; j < NQ; j++) acc[j] += con[u][j];
+            for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] += acc[j];
         }
+        __threadfence();
+        __syncthreads();
     }
 }
 
@@ -459,7 +488,7 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
                            (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,
                            d.adj_list_n);
     if (probe_src && np > 0)
-        hipLaunchKernelGGL((k_adjoint_probes<K>), dim3(1), dim3(64), 0, s, (const typename C::store*)f_t, (R*)lam,
+        hipLaunchKernelGGL((k_adjoint_probes<K>), dim3(1), dim3(PROBE_CHUNK), 0, s, (const typename C::store*)f_t, (R*)lam,
                            d.mask, g, P, probes, np, (const R*)probe_src);
     return hipGetLastError();
 }

@@ -171,6 +171,9 @@ struct Phys {
     R W2[3];       // 2 Omega, Omega the rotation vector in lattice units (Coriolis)
     int has_rot;   // W2 != 0
     int has_force; // F != 0 or has_rot: the Guo source is applied
+    int sponge_w;  // width W of the sponge / buffer layers; 0: off
+    R sponge_s;    // strength s_max at the layer next to the face
+    const double* target;  // per-height face profiles [6][nz][3]: the nudging targets
 };
 
 // Body force on one cell: the uniform force plus the Coriolis force of the
@@ -529,6 +532,60 @@ __device__ inline void collide_pairs(R* h, const Phys<R>& P, R& drho_o, R& ux, R
     }
     drho_o = drho;
     tau_o = tau;
+}
+
+// Sponge and buffer nudging after the collision: next to every INFLOW_EQ
+// face except the ground, a cell at distance d = 1..W from the face layer
+// has strength s = s_max ((W + 1 - d) / W)^2 (the largest over the faces,
+// the lower-numbered face on ties), and its populations move by
+// s (feq(rho, u_t) - feq(rho, u)), u_t the face's profile at the cell's
+// height (the top row for z+).  The density parts of the two equilibria
+// cancel, so the shift is w rho [-1.5 (|u_t|^2 - |u|^2) + 4.5 (e_t^2 - e^2)
+// + 3 (e_t - e)] per direction, times s and the storage scale.
+template <typename R, int SC>
+__device__ inline void nudge_at(R* h, const Phys<R>& P, const Geo& g, int x, int y, int z, R drho, R ux, R uy,
+                                R uz)
+{
+    const int dist[6] = {x, g.nx - 1 - x, y, g.ny - 1 - y, z, g.nz - 1 - z};
+    R best = R(0);
+    int face = -1;
+#pragma unroll
+    for (int F = 0; F < 6; F++) {
+        if (F == 4 || g.face[F] != F_INFLOW) continue;
+        const int d = dist[F];
+        if (d < 1 || d > P.sponge_w) continue;
+        const R r = R(P.sponge_w + 1 - d) / R(P.sponge_w);
+        const R s = P.sponge_s * r * r;
+        if (s > best) {
+            best = s;
+            face = F;
+        }
+    }
+    if (face < 0) return;
+    const double* pt = P.target + ((long long)face * g.nz + (face == 5 ? g.nz - 1 : z)) * 3;
+    const R tx = R(pt[0]), ty = R(pt[1]), tz = R(pt[2]);
+    const R k = best * R(SC) * (P.rho0 + drho);
+    const R dus = R(-1.5) * ((tx * tx + ty * ty + tz * tz) - (ux * ux + uy * uy + uz * uz));
+    h[0] += k * weight<R>(0) * dus;
+#pragma unroll
+    for (int i = 1; i < NQ; i += 2) {
+        const V3 c = dirv(i);
+        const R et = R(c.x) * tx + R(c.y) * ty + R(c.z) * tz;
+        const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
+        const R ev = weight<R>(i) * (dus + R(4.5) * (et * et - e * e));
+        const R od = weight<R>(i) * (R(3) * (et - e));
+        h[i] += k * (ev + od);
+        h[i + 1] += k * (ev - od);
+    }
+}
+
+// The collision of one interior cell at (x, y, z), nudging included.
+template <typename R, int SC>
+__device__ inline void collide_at(R* h, const Phys<R>& P, const Geo& g, int x, int y, int z, R& drho, R& ux, R& uy,
+                                  R& uz, R& tau)
+{
+    collide_pairs<R, SC>(h, P, drho, ux, uy, uz, tau);
+    if (P.sponge_w > 0) nudge_at<R, SC>(h, P, g, x, y, z, drho, ux, uy, uz);
 }
 
 // --------------------------------------------------------------------------

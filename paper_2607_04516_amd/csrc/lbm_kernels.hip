@@ -104,7 +104,7 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
             }
         });
         R drho, tau;
-        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+        collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
         // scatter
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
@@ -194,7 +194,7 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
             h[I] = C::raw(src[idx]);
         });
         R drho, ux, uy, uz, tau;
-        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+        collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             constexpr V3 c = dirv(I);

@@ -25,6 +25,8 @@ struct DevCtx {
     long long adj_list_n;
     double tau0, c_smag, delta, rho0, force[3];
     double omega[3];      // rotation vector in lattice units (Coriolis); zero: none
+    int sponge_w;         // sponge / buffer layer width; 0: off
+    double sponge_s;      // its strength s_max
 };
 
 // Collision parameters of a context in the codec's arithmetic type.
@@ -42,6 +44,9 @@ static inline Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
     }
     P.has_rot = (d.omega[0] != 0.0 || d.omega[1] != 0.0 || d.omega[2] != 0.0) ? 1 : 0;
     P.has_force = (P.has_rot || d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+    P.sponge_w = d.sponge_s > 0.0 ? d.sponge_w : 0;
+    P.sponge_s = R(d.sponge_s);
+    P.target = d.prof;
     return P;
 }
 
@@ -73,6 +78,11 @@ hipError_t launch_probe_points(const DevCtx& d, int phase, const float* pts, int
 hipError_t launch_probe_cells(const DevCtx& d, int phase, const int* cells, int np, void* acc, hipStream_t s);
 int mass_blocks(const Geo& g);
 hipError_t launch_mass(const DevCtx& d, int phase, double* partial, double* out5, hipStream_t s);
+// Net outward flux over the boundary cells (slot, face) of uin into phi_out[0]
+// (device); with apply, also the uniform normal shift that zeroes it.
+hipError_t launch_flux_balance(const int* slot, const int* face, long long n, double* uin, double* partial,
+                               double* phi_out, int apply, hipStream_t s);
+int flux_partial_count();
 hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
                           int np, const void* probe_src, void* g_inflow, hipStream_t s);
 

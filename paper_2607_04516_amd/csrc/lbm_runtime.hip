@@ -35,6 +35,11 @@ struct lbm_ctx {
     std::vector<uint64_t> bits_host;  // solid bits, kept for the turbulence generator
     VkGen* vk = nullptr;              // synthetic inflow generator, NULL when off
     lbm_turbulence vkp{};
+    // flux balancing: boundary cells (inflow entry, face), partial sums, phi
+    int flux_mode = 0;
+    int* flux_cells = nullptr;        // [2][n_flux]: slot, then face
+    long long n_flux = -1;            // -1: list not built yet
+    double* flux_red = nullptr;       // partial sums, then phi at the end
     bool prof_set[6] = {false, false, false, false, false, false};
     double* u0 = nullptr;   // device [nz][3] scratch for initialisation
     int* probes = nullptr;  // device [np][3]
@@ -101,7 +106,7 @@ static void free_all(lbm_ctx* c)
     vk_destroy(c->vk);
     c->vk = nullptr;
     void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
-                    c->push_list, c->adj_list, c->uin};
+                    c->push_list, c->adj_list, c->uin, c->flux_cells, c->flux_red};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -116,6 +121,9 @@ static void free_all(lbm_ctx* c)
     c->push_list = nullptr;
     c->adj_list = nullptr;
     c->uin = nullptr;
+    c->flux_cells = nullptr;
+    c->flux_red = nullptr;
+    c->n_flux = -1;
 }
 
 static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
@@ -207,6 +215,8 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         c->d.force[a] = params->body_force[a];
         c->d.omega[a] = 0.0;
     }
+    c->d.sponge_w = 0;
+    c->d.sponge_s = 0.0;
 
     // bit-packed solid mask, cell counts
     std::vector<uint64_t> bits((size_t)g.wpr * g.ny * g.nz, 0ull);
@@ -435,6 +445,143 @@ int lbm_set_turbulence(lbm_ctx* c, const lbm_turbulence* p)
     return LBM_OK;
 }
 
+int lbm_set_sponge(lbm_ctx* c, int32_t width, double strength)
+{
+    if (!c) return LBM_EINVAL;
+    const Geo& g = c->d.g;
+    const int lim = std::min(g.nx, std::min(g.ny, g.nz)) - 2;
+    if (width < 0 || width > lim || !(strength >= 0.0 && strength <= 1.0))
+        return fail(c, LBM_EINVAL, "sponge width outside [0, min(n) - 2] or strength outside [0, 1]");
+    c->d.sponge_w = width;
+    c->d.sponge_s = strength;
+    return LBM_OK;
+}
+
+// Non-solid cells of the INFLOW_EQ faces, each on its owning face.
+static int build_flux_cells(lbm_ctx* c)
+{
+    if (c->n_flux >= 0) return LBM_OK;
+    const Geo& g = c->d.g;
+    std::vector<int> sl, fc;
+    for (int z = 0; z < g.nz; z++)
+        for (int y = 0; y < g.ny; y++)
+            for (int x = 0; x < g.nx; x++) {
+                const int F = inflow_face_of(g, x, y, z);
+                if (F < 0) continue;
+                if ((c->bits_host[((size_t)y + (size_t)g.ny * z) * g.wpr + (x >> 6)] >> (x & 63)) & 1ull) continue;
+                sl.push_back((int)inflow_slot(g, F, x, y, z));
+                fc.push_back(F);
+            }
+    const long long n = (long long)sl.size();
+    sl.insert(sl.end(), fc.begin(), fc.end());
+    int rc;
+    if ((rc = device_alloc(c, (void**)&c->flux_cells, sl.size() * sizeof(int), "flux cells")) != LBM_OK) return rc;
+    if ((rc = device_alloc(c, (void**)&c->flux_red, (flux_partial_count() + 2) * sizeof(double), "flux sums")) !=
+        LBM_OK)
+        return rc;
+    if (!sl.empty())
+        HIPCHK(c, hipMemcpy(c->flux_cells, sl.data(), sl.size() * sizeof(int), hipMemcpyHostToDevice), "flux cells");
+    c->n_flux = n;
+    return LBM_OK;
+}
+
+// Net outward flux of the per-height profiles over the boundary cells.
+static double profile_flux(const lbm_ctx* c, long long* count)
+{
+    const Geo& g = c->d.g;
+    double phi = 0.0;
+    long long n = 0;
+    for (int z = 0; z < g.nz; z++)
+        for (int y = 0; y < g.ny; y++)
+            for (int x = 0; x < g.nx; x++) {
+                const int F = inflow_face_of(g, x, y, z);
+                if (F < 0) continue;
+                if ((c->bits_host[((size_t)y + (size_t)g.ny * z) * g.wpr + (x >> 6)] >> (x & 63)) & 1ull) continue;
+                const double v = c->prof_host[((size_t)F * g.nz + z) * 3 + (F >> 1)];
+                phi += (F & 1) ? v : -v;
+                n++;
+            }
+    if (count) *count = n;
+    return phi;
+}
+
+int lbm_net_flux(lbm_ctx* c, double* phi)
+{
+    if (!c) return LBM_EINVAL;
+    if (!phi) return fail(c, LBM_EINVAL, "NULL output");
+    int rc = build_flux_cells(c);
+    if (rc != LBM_OK) return rc;
+    *phi = 0.0;
+    if (c->n_flux == 0) return LBM_OK;
+    double* out = c->flux_red + flux_partial_count();
+    HIPCHK(c, launch_flux_balance(c->flux_cells, c->flux_cells + c->n_flux, c->n_flux, c->uin, c->flux_red, out, 0,
+                                  c->stream), "net flux");
+    HIPCHK(c, hipMemcpyAsync(phi, out, sizeof(double), hipMemcpyDeviceToHost, c->stream), "net flux");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "net flux");
+    return LBM_OK;
+}
+
+int lbm_balance_flux(lbm_ctx* c, int32_t mode, double* phi_before, double* phi_after)
+{
+    if (!c) return LBM_EINVAL;
+    if (mode < 0 || mode > 2) return fail(c, LBM_EINVAL, "flux balancing mode must be 0, 1 or 2");
+    int rc = build_flux_cells(c);
+    if (rc != LBM_OK) return rc;
+    const Geo& g = c->d.g;
+    if (mode == 0) {
+        c->flux_mode = 0;
+        if (phi_before && (rc = lbm_net_flux(c, phi_before)) != LBM_OK) return rc;
+        if (phi_after) *phi_after = phi_before ? *phi_before : 0.0;
+        return LBM_OK;
+    }
+    if (mode == 1) {
+        long long n = 0;
+        const double phi = profile_flux(c, &n);
+        if (phi_before) *phi_before = phi;
+        if (n > 0) {
+            const double delta = phi / (double)n;
+            for (int F = 0; F < 6; F++) {
+                if (g.face[F] != LBM_INFLOW_EQ) continue;
+                for (int z = 0; z < g.nz; z++)
+                    c->prof_host[((size_t)F * g.nz + z) * 3 + (F >> 1)] -= (F & 1) ? delta : -delta;
+            }
+            HIPCHK(c, hipMemcpyAsync(c->prof, c->prof_host.data(), 18 * (size_t)g.nz * sizeof(double),
+                                     hipMemcpyHostToDevice, c->stream), "upload profiles");
+            HIPCHK(c, hipStreamSynchronize(c->stream), "upload profiles");
+            for (int F = 0; F < 6; F++)
+                if ((rc = broadcast_profile(c, F)) != LBM_OK) return rc;
+            if (c->vk) {
+                VkGen* v = nullptr;
+                std::string err;
+                rc = vk_create(&v, c->vkp, c->d.g, c->bits_host, c->prof_host, err);
+                if (rc != LBM_OK) return fail(c, rc, err);
+                vk_destroy(c->vk);
+                c->vk = v;
+            }
+        }
+        if (phi_after) *phi_after = profile_flux(c, nullptr);
+        return LBM_OK;
+    }
+    // mode 2: balance the current field now, and before every step from now on
+    c->flux_mode = 2;
+    if (c->n_flux == 0) {
+        if (phi_before) *phi_before = 0.0;
+        if (phi_after) *phi_after = 0.0;
+        return LBM_OK;
+    }
+    double* out = c->flux_red + flux_partial_count();
+    double h[2];
+    HIPCHK(c, launch_flux_balance(c->flux_cells, c->flux_cells + c->n_flux, c->n_flux, c->uin, c->flux_red, out, 1,
+                                  c->stream), "flux balance");
+    HIPCHK(c, launch_flux_balance(c->flux_cells, c->flux_cells + c->n_flux, c->n_flux, c->uin, c->flux_red, out + 1,
+                                  0, c->stream), "net flux");
+    HIPCHK(c, hipMemcpyAsync(h, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "flux copy");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "flux copy");
+    if (phi_before) *phi_before = h[0];
+    if (phi_after) *phi_after = h[1];
+    return LBM_OK;
+}
+
 int lbm_turbulence_info(lbm_ctx* c, int64_t* n_active, double* u_ref, double* e_c)
 {
     if (!c) return LBM_EINVAL;
@@ -499,6 +646,9 @@ static int one_step(lbm_ctx* c)
     int rc;
     if (c->stats && c->stats_stride > 0 && (c->t % c->stats_stride) == 0) st = c->stats;
     HIPCHK(c, vk_apply(c->vk, c->uin, c->t, c->stream), "synthetic inflow");
+    if (c->flux_mode == 2)
+        HIPCHK(c, launch_flux_balance(c->flux_cells, c->flux_cells + c->n_flux, c->n_flux, c->uin, c->flux_red,
+                                      c->flux_red + flux_partial_count(), 1, c->stream), "flux balance");
     if (c->phase == 0) {
         if ((rc = mark(c)) != LBM_OK) return rc;
         HIPCHK(c, launch_step(c->d, 0, st, c->stream), "even step");
@@ -691,6 +841,7 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
     }
     if (probe_src && c->np == 0) return fail(c, LBM_ESTATE, "probe source without registered probes");
     if (c->vk) return fail(c, LBM_ESTATE, "adjoint step with synthetic inflow turbulence on");
+    if (c->d.sponge_w > 0 && c->d.sponge_s > 0.0) return fail(c, LBM_ESTATE, "adjoint step with the sponge on");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
     HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, c->probes, c->np, probe_src, g_inflow, c->stream),

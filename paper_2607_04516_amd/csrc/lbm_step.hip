@@ -120,7 +120,7 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
         h[I] = C::raw(ld_pop((const T*)(base + I * sb + off)));
     });
     R drho, ux, uy, uz, tau;
-    collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+    collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         st_pop((T*)(base + I * sb + off), C::pack(h[opp(I)]));
@@ -189,7 +189,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
             h[I] = C::raw(ld_pop((const T*)(sbI + off)));
         });
         R drho, ux, uy, uz, tau;
-        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+        collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             constexpr V3 c = dirv(I);
@@ -243,7 +243,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
         uz = R(p[2]);
     } else {
         R drho, tau;
-        collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+        collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
     }
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -300,7 +300,7 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
         h[I] = C::raw(ld_pop((const T*)(sbase + I * sb + off)));
     });
     R drho, ux, uy, uz, tau;
-    collide_pairs<R, C::SC>(h, P, drho, ux, uy, uz, tau);
+    collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
     if (any == 0) {
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;

@@ -96,7 +96,7 @@ def test_boundary_field_matches_oracle(case):
     np.testing.assert_allclose(e_c, gen.e_c, atol=1e-14)
     for t in (0, 1, 2, 5, 9):
         if t:
-            lat.step(t - lat.time() + 1)     # the last step started from time t
+            lat.step(t - lat.time + 1)     # the last step started from time t
         fo = gen.field(t)
         for face in (0, 2, 5):
             got = lat.get_inflow(face)
