@@ -641,19 +641,22 @@ __device__ inline void load_rows(RowWin& W, const uint64_t* mask, const Geo& g, 
     const bool last = (cx + 1 >= g.wpr);
     const int l_last = (g.nx - 1) - cx * 64;  // lane of x = nx - 1 when this chunk holds it
     const uint64_t pad = (xp_wall && last && l_last < 63) ? (~0ull << (l_last + 1)) : 0ull;
+    // Every word is computed as a value (loads from a clamped, always valid
+    // index, then selects), never stored under a branch: that keeps the
+    // window in scalar registers instead of a private (scratch) array.
 #pragma unroll
     for (int dz = -1; dz <= 1; dz++)
 #pragma unroll
         for (int dy = -1; dy <= 1; dy++) {
             const int yy = y + dy, zz = z + dz;
-            if (yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) {
-                W.c[dz + 1][dy + 1] = W.p[dz + 1][dy + 1] = W.n[dz + 1][dy + 1] = ~0ull;
-                continue;
-            }
-            const long long w = ((long long)yy + (long long)g.ny * zz) * g.wpr + cx;
-            W.c[dz + 1][dy + 1] = mask_word(mask, w) | pad;
-            W.p[dz + 1][dy + 1] = cx > 0 ? mask_word(mask, w - 1) : (xm_wall ? ~0ull : 0ull);
-            W.n[dz + 1][dy + 1] = !last ? mask_word(mask, w + 1) : (xp_wall ? ~0ull : 0ull);
+            const bool out = yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz;
+            const long long w = out ? (long long)cx : ((long long)yy + (long long)g.ny * zz) * g.wpr + cx;
+            const uint64_t wc = mask_word(mask, w);
+            const uint64_t wp = mask_word(mask, cx > 0 ? w - 1 : w);
+            const uint64_t wn = mask_word(mask, !last ? w + 1 : w);
+            W.c[dz + 1][dy + 1] = out ? ~0ull : (wc | pad);
+            W.p[dz + 1][dy + 1] = out ? ~0ull : (cx > 0 ? wp : (xm_wall ? ~0ull : 0ull));
+            W.n[dz + 1][dy + 1] = out ? ~0ull : (!last ? wn : (xp_wall ? ~0ull : 0ull));
         }
 }
 
