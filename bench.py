@@ -40,11 +40,13 @@ def algorithmic_bytes(lat, storage):
     return interior * 2 * NQ * b + (fluid - interior) * NQ * b
 
 
-def time_forward(w, storage, steps, warmup):
+def time_forward(w, storage, steps, warmup, setup=None):
     import torch
 
     from paper_2607_04516_amd import binding
     lat = binding.from_workload(w, storage=storage)
+    if setup is not None:
+        setup(lat)
     lat.step(warmup)
     torch.cuda.synchronize()
     lat.profile(True)
@@ -120,6 +122,72 @@ def time_adjoint(steps=1000, every=50):
             "loss": float(L), "grad_norm": float(np.linalg.norm(g))}
 
 
+FEATURE_NAMES = ("coriolis", "von_karman_inflow", "sponge", "flux_balance_every_step")
+
+
+def apply_feature(lat, name):
+    """The paper's additions to the step (App. E, App. F, Sec. 2.2), on the bench grid."""
+    from paper_2607_04516_amd import binding
+    if name == "coriolis":            # Earth rotation at 23.113 N, dt = 0.01 s
+        lat.set_rotation(binding.earth_rotation(23.113, 0.01))
+    elif name == "von_karman_inflow":  # 64 modes per face, L = 20 cells, 10% intensity
+        lat.set_turbulence(n_modes=64, length_scale=20.0, intensity=0.1, seed=1)
+    elif name == "sponge":             # 16-cell layers next to the inflow faces
+        lat.set_sponge(16, 0.05)
+    elif name == "flux_balance_every_step":
+        lat.balance_flux(2)
+    else:
+        raise ValueError(name)
+
+
+def time_features(w, steps, warmup):
+    """FP32 step rate with each source or stabiliser switched on alone, and all together."""
+    out = {}
+    for name in FEATURE_NAMES + ("all",):
+        def setup(lat, name=name):
+            for k in (FEATURE_NAMES if name == "all" else (name,)):
+                apply_feature(lat, k)
+        r = time_forward(w, "f32", steps, warmup, setup)
+        out[name] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4)}
+    return out
+
+
+def copy_bandwidth():
+    """Device-to-device copy of 4 GiB, best of 5: an achievable HBM figure on this machine."""
+    import torch
+    a = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
+def traffic_from_profiles(storage):
+    """HBM bytes per step-kernel launch from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_even_k_odd_urban_km_800x800x128.json")
+    if not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2607_04516_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    if rec.get("sources_sha256") != h.hexdigest() or storage not in rec.get("per_launch_bytes", {}):
+        return None, rec.get("sources_sha256")
+    return rec["per_launch_bytes"][storage], rec.get("sources_sha256")
+
+
 def cpu_baseline(w, seconds=12.0, crop=(160, 160)):
     """The FP64 oracle (single thread) on a crop of the workload: the first
     crop[0] x crop[1] columns with the full height, same faces and profiles."""
@@ -158,6 +226,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost run")
+    ap.add_argument("--no-features", action="store_true", help="skip the Coriolis / inflow / stabiliser runs")
     ap.add_argument("--nx", type=int, default=800)
     ap.add_argument("--ny", type=int, default=800)
     ap.add_argument("--nz", type=int, default=128)
@@ -191,6 +260,16 @@ def main():
             print(f"[bench] {s}: {r['mlups']:.0f} MLUPS, {r['achieved_gbs']:.0f} GB/s", file=sys.stderr,
                   flush=True)
 
+    feats = None
+    if not args.no_features:
+        print("[bench] features", file=sys.stderr, flush=True)
+        feats = time_features(w, min(args.steps, 100), args.warmup)
+        print(f"[bench] features: {feats}", file=sys.stderr, flush=True)
+
+    copy_gbs = copy_bandwidth()
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    traffic, _ = traffic_from_profiles(args.storage)
+
     adj = None
     if not args.no_adjoint:
         print("[bench] adjoint workload", file=sys.stderr, flush=True)
@@ -220,14 +299,20 @@ def main():
                    "cells": w.cells, "fluid_cells": res["fluid_cells"], "storage": args.storage,
                    "layout": "SoA [19][z][y][x_pitch64], in-place A-A"},
         "roofline": {"bound": "hbm", "achieved": round(res["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "lbm::k_step (even/odd A-A launches)",
+                     "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (res["kernel_ms"] * 1e-3) / 1e9, 1),
+                     "traffic_bytes_per_launch": traffic,
+                     "kernel": "lbm::k_even / lbm::k_odd (alternating A-A launches, averaged)",
                      "kernel_ms": round(res["kernel_ms"], 4),
-                     "bytes_per_launch": res["bytes_per_launch"]},
+                     "bytes_per_launch": res["bytes_per_launch"],
+                     "device_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(res["achieved_gbs"] / copy_gbs, 4)},
         "cpu_baseline": cpu,
     }
     if extra:
         line["storage_forms"] = extra
+    if feats:
+        line["features"] = feats
     if adj:
         line["adjoint"] = adj
     print(json.dumps(line), flush=True)
