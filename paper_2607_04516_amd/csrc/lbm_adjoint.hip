@@ -270,8 +270,9 @@ k_adjoint_cells(const typename Codec<K>::store* __restrict__ f_t, const typename
 template <int K>
 __global__ void __launch_bounds__(256)
 k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
-               typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask, Geo g,
-               Phys<typename Codec<K>::real> P, long long nwaves)
+               typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
+               const int* __restrict__ wave_idx, const uint64_t* __restrict__ wave_tab, Geo g,
+               Phys<typename Codec<K>::real> P, StepOff O, long long nwaves)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -285,28 +286,22 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
     const Box B = main_box(g, 1);
     if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
     const int x = cx * 64 + lane;
-    RowWin W;
-    load_rows(W, mask, g, cx, y, z);
+    const WaveMask WM = wave_mask(wave_idx, wave_tab, wave);
+    const uint64_t own = mask_word(mask, row * g.wpr + cx);
     if (x < B.x0 || x > B.x1) return;
     const long long cell = (long long)x + (long long)g.nx * row;
-    const long long sb = g.N * (long long)sizeof(R);
     const uint32_t off = (uint32_t)cell * (uint32_t)sizeof(R);
     const char* lbase = (const char*)lam_next;
-    if ((W.c[1][1] >> lane) & 1ull) {
+    if ((own >> lane) & 1ull) {
 #pragma unroll
         for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = R(0);
         return;
     }
-    uint64_t any = 0;
-    adj_static_for<1, NQ>([&](auto ic) { any |= solid_src_mask<decltype(ic)::value>(W); });
-    any = uniform_u64(any);
     R ls[NQ], h[NQ];
-    if (any == 0) {
+    if (!WM.m) {
         adj_static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            constexpr V3 c = dirv(I);
-            const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
-            ls[opp(I)] = *(const R*)(lbase + opp(I) * sb - d * (long long)sizeof(R) + off);
+            ls[opp(I)] = *(const R*)(lbase + O.odd[I] + off);
         });
     } else {
         adj_static_for<0, NQ>([&](auto ic) {
@@ -314,13 +309,8 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
             if constexpr (I == 0) {
                 ls[0] = *(const R*)(lbase + off);
             } else {
-                constexpr V3 c = dirv(I);
-                constexpr int lo = I < opp(I) ? I : opp(I);
-                const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
-                const uint32_t on = off + (uint32_t)((opp(I) - lo) * sb - d * (long long)sizeof(R));
-                const uint32_t oo = off + (uint32_t)((I - lo) * sb);
-                const uint32_t so = lane_select(on, oo, solid_src_mask<I>(W));
-                ls[opp(I)] = *(const R*)(lbase + lo * sb + so);
+                const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], WM.template get<I>());
+                ls[opp(I)] = *(const R*)(lbase + O.lo[I] + so);
             }
         });
     }
@@ -481,8 +471,10 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
         }
     }
     const long long nwaves = (long long)g.ncx * g.ny * g.nz;
+    const StepOff O = step_offsets<R>(g.N, g.nx, g.ny);
     hipLaunchKernelGGL((k_adjoint_main<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
-                       (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, nwaves);
+                       (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, d.wave_idx, d.wave_tab, g,
+                       P, O, nwaves);
     if (d.adj_list_n > 0)
         hipLaunchKernelGGL((k_adjoint_cells<K>), dim3((unsigned)((d.adj_list_n + 255) / 256)), dim3(256), 0, s,
                            (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,

@@ -602,6 +602,29 @@ __device__ inline uint64_t mask_word(const uint64_t* mask, long long i)
     return ((const const_u64*)mask)[i];
 }
 
+typedef const int __attribute__((address_space(4))) const_i32;
+
+// Solid-source masks of one wave (64 cells of a row) for directions 1..18,
+// bit l set when the pull source of lane l is solid (WALL faces included),
+// read from a per-grid table built once (see build_wave_masks): a wave with
+// no solid neighbour has no entry.  Wave-uniform, so scalar loads.
+struct WaveMask {
+    const uint64_t* m;  // 18 words, or nullptr
+    template <int I>
+    __device__ uint64_t get() const
+    {
+        return m ? ((const const_u64*)m)[I - 1] : 0ull;
+    }
+};
+
+__device__ inline WaveMask wave_mask(const int* __restrict__ idx, const uint64_t* __restrict__ tab, long long wave)
+{
+    const int k = ((const const_i32*)idx)[wave];
+    WaveMask w;
+    w.m = k >= 0 ? tab + 18ll * k : nullptr;
+    return w;
+}
+
 // A wave-uniform 64-bit value, made explicitly uniform (readfirstlane of
 // each half; the builtin returns int, so go through uint32_t before
 // widening or the low half would be sign-extended).

@@ -23,6 +23,8 @@ struct DevCtx {
     long long push_list_n;
     const unsigned* adj_list;  // canonical indices of the two-layer face shell (general-path adjoint)
     long long adj_list_n;
+    const int* wave_idx;       // per wave (chunk, row): entry in wave_tab, -1 without solid neighbour
+    const uint64_t* wave_tab;  // [entries][18] solid-source masks
     double tau0, c_smag, delta, rho0, force[3];
     double omega[3];      // rotation vector in lattice units (Coriolis); zero: none
     int sponge_w;         // sponge / buffer layer width; 0: off
@@ -48,6 +50,37 @@ static inline Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
     P.sponge_s = R(d.sponge_s);
     P.target = d.prof;
     return P;
+}
+
+// Byte offsets of the population slots a wave touches, fixed per grid and
+// codec and computed once per launch on the host (otherwise every wave
+// rebuilds them with 64-bit scalar arithmetic).  Slice stride sb = S (padded
+// in-place layout) or N (canonical layout) times the store size; d_I is the
+// element offset of the neighbour x + c_I.
+struct StepOff {
+    long long even[NQ];  // I sb: slot I of the own cell
+    long long odd[NQ];   // opp(I) sb - d_I: slot opp(I) of the neighbour x - c_I
+    long long lo[NQ];    // min(I, opp(I)) sb
+    uint32_t on[NQ];     // (opp(I) - lo) sb - d_I, relative to lo (mod 2^32)
+    uint32_t oo[NQ];     // (I - lo) sb
+};
+
+template <typename T>
+static StepOff step_offsets(long long slice, long long rowlen, long long ny)
+{
+    StepOff o;
+    const long long sb = slice * (long long)sizeof(T);
+    for (int i = 0; i < NQ; i++) {
+        const V3 c = dirv(i);
+        const int lo = i < opp(i) ? i : opp(i);
+        const long long d = ((long long)c.x + rowlen * (c.y + ny * c.z)) * (long long)sizeof(T);
+        o.even[i] = i * sb;
+        o.odd[i] = opp(i) * sb - d;
+        o.lo[i] = lo * sb;
+        o.on[i] = (uint32_t)((opp(i) - lo) * sb - d);
+        o.oo[i] = (uint32_t)((i - lo) * sb);
+    }
+    return o;
 }
 
 // Host copy of the odd kernel's test for waves it leaves to the general
@@ -83,6 +116,9 @@ hipError_t launch_mass(const DevCtx& d, int phase, double* partial, double* out5
 hipError_t launch_flux_balance(const int* slot, const int* face, long long n, double* uin, double* partial,
                                double* phi_out, int apply, hipStream_t s);
 int flux_partial_count();
+// Wave-mask table: pass 0 writes a 0/1 flag per wave into idx (solid
+// neighbour or not); pass 1 fills tab for the waves whose idx >= 0.
+hipError_t launch_wave_masks(const DevCtx& d, int* idx, uint64_t* tab, int pass, hipStream_t s);
 hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
                           int np, const void* probe_src, void* g_inflow, hipStream_t s);
 

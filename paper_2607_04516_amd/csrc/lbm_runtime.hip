@@ -49,6 +49,8 @@ struct lbm_ctx {
     unsigned* odd_list = nullptr;
     unsigned* push_list = nullptr;
     unsigned* adj_list = nullptr;
+    int* wave_idx = nullptr;        // per wave: entry in wave_tab or -1
+    uint64_t* wave_tab = nullptr;   // solid-source masks of waves with a solid neighbour
     void* stats = nullptr;
     int stats_stride = 0;
     int64_t fluid = 0, interior = 0;
@@ -106,7 +108,7 @@ static void free_all(lbm_ctx* c)
     vk_destroy(c->vk);
     c->vk = nullptr;
     void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
-                    c->push_list, c->adj_list, c->uin, c->flux_cells, c->flux_red};
+                    c->push_list, c->adj_list, c->uin, c->flux_cells, c->flux_red, c->wave_idx, c->wave_tab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -124,7 +126,10 @@ static void free_all(lbm_ctx* c)
     c->flux_cells = nullptr;
     c->flux_red = nullptr;
     c->n_flux = -1;
+    c->wave_idx = nullptr;
+    c->wave_tab = nullptr;
 }
+
 
 static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
 {
@@ -134,6 +139,32 @@ static int device_alloc(lbm_ctx* c, void** ptr, size_t bytes, const char* what)
         return fail(c, LBM_ENOMEM, std::string("out of device memory allocating ") + what);
     }
     if (e != hipSuccess) return hip_fail(c, e, what);
+    return LBM_OK;
+}
+
+// Per-wave solid-source masks (static geometry): flags on the device, a
+// prefix numbering on the host, then the compact table.
+static int build_wave_masks(lbm_ctx* c)
+{
+    const Geo& g = c->d.g;
+    const long long nwaves = (long long)g.ncx * g.ny * g.nz;
+    int rc;
+    if ((rc = device_alloc(c, (void**)&c->wave_idx, (size_t)nwaves * sizeof(int), "wave masks")) != LBM_OK) return rc;
+    HIPCHK(c, launch_wave_masks(c->d, c->wave_idx, nullptr, 0, c->stream), "wave mask flags");
+    std::vector<int> h((size_t)nwaves);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->wave_idx, h.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream),
+           "wave mask flags");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "wave mask flags");
+    long long n = 0;
+    for (long long w = 0; w < nwaves; w++) h[(size_t)w] = h[(size_t)w] ? (int)n++ : -1;
+    if ((rc = device_alloc(c, (void**)&c->wave_tab, (size_t)n * 18 * sizeof(uint64_t), "wave masks")) != LBM_OK)
+        return rc;
+    HIPCHK(c, hipMemcpyAsync(c->wave_idx, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
+           "wave mask index");
+    HIPCHK(c, launch_wave_masks(c->d, c->wave_idx, c->wave_tab, 1, c->stream), "wave mask table");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "wave mask table");
+    c->d.wave_idx = c->wave_idx;
+    c->d.wave_tab = c->wave_tab;
     return LBM_OK;
 }
 
@@ -321,6 +352,12 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->d.prof = c->prof;
     c->d.uin = c->uin;
     c->bits_host = std::move(bits);
+    if ((rc = build_wave_masks(c)) != LBM_OK) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return rc;
+    }
     if ((rc = lbm_reset(c, nullptr)) != LBM_OK) {
         g_create_error = c->err;
         free_all(c);

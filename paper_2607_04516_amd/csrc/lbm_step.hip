@@ -83,7 +83,7 @@ __device__ inline void add_stats(R* stats, const Geo& g, int x, int y, int z, R 
 template <int K, bool STATS>
 __global__ void __launch_bounds__(256)
 k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin, Geo g,
-       Phys<typename Codec<K>::real> P, typename Codec<K>::real* stats, long long nwaves, long long nbp)
+       Phys<typename Codec<K>::real> P, StepOff O, typename Codec<K>::real* stats, long long nwaves, long long nbp)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -98,7 +98,6 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
     const uint64_t wrow = mask_word(mask, row * g.wpr + cx);
     if (x >= g.nx || ((wrow >> lane) & 1ull)) return;
 
-    const long long sb = g.S * (long long)sizeof(T);
     char* base = (char*)f;
     const uint32_t off = (uint32_t)((long long)x + (long long)g.pitch * row) * (uint32_t)sizeof(T);
     R h[NQ];
@@ -111,19 +110,19 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
         }
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            st_pop((T*)(base + I * sb + off), C::pack(h[opp(I)]));
+            st_pop((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
         });
         return;
     }
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        h[I] = C::raw(ld_pop((const T*)(base + I * sb + off)));
+        h[I] = C::raw(ld_pop((const T*)(base + O.even[I] + off)));
     });
     R drho, ux, uy, uz, tau;
     collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        st_pop((T*)(base + I * sb + off), C::pack(h[opp(I)]));
+        st_pop((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
 }
@@ -138,8 +137,9 @@ __device__ inline bool odd_general_wave(const Geo& g, int cx, int y, int z)
 // ---------------------------------------------------------------- odd step
 template <int K, bool STATS>
 __global__ void __launch_bounds__(256)
-k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin,
-      const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P,
+k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int* __restrict__ wave_idx,
+      const uint64_t* __restrict__ wave_tab, const double* __restrict__ uin,
+      const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P, StepOff O,
       typename Codec<K>::real* stats, long long nwaves, long long nbp)
 {
     using C = Codec<K>;
@@ -157,45 +157,56 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
     const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane l_out is an x+ outflow or wall cell
     const int l_out = (g.nx - 1) - cx * 64;
 
+    // Solid-source masks: 16-bit storage leaves the kernel issue-bound, so it
+    // reads them from the per-wave table (18 scalar loads, no mask
+    // arithmetic); wider storage is bandwidth-bound and builds them from the
+    // mask rows, whose words neighbouring waves share in the scalar cache
+    // (the table entry is a cold load ahead of every wave's first access).
+    constexpr bool ROWS = sizeof(T) >= 4;
     RowWin W;
-    load_rows(W, mask, g, cx, y, z);
-    if (x >= g.nx || ((W.c[1][1] >> lane) & 1ull)) return;
+    WaveMask WM{nullptr};
+    uint64_t own;
+    bool solid_any;
+    if constexpr (ROWS) {
+        load_rows(W, mask, g, cx, y, z);
+        own = W.c[1][1];
+        uint64_t a = 0;
+        sfor<1, NQ>([&](auto ic) { a |= solid_src_mask<decltype(ic)::value>(W); });
+        solid_any = uniform_u64(a) != 0;
+    } else {
+        WM = wave_mask(wave_idx, wave_tab, wave);
+        own = mask_word(mask, row * g.wpr + cx);
+        solid_any = WM.m != nullptr;
+    }
+    if (x >= g.nx || ((own >> lane) & 1ull)) return;
 
     // bounce mask of direction I: bit l set when lane l must use its own
     // slot (solid neighbour, or an x-face lane's face-crossing direction)
     auto bmask = [&](auto ic) -> uint64_t {
         constexpr int I = decltype(ic)::value;
         constexpr V3 c = dirv(I);
-        uint64_t m = solid_src_mask<I>(W);
+        uint64_t m;
+        if constexpr (ROWS) m = solid_src_mask<I>(W);
+        else m = WM.template get<I>();
         if constexpr (c.x == 1) { if (x_lo) m |= 1ull; }
         if constexpr (c.x == -1) { if (x_hi) m |= 1ull << l_out; }
         return m;
     };
-    uint64_t any = 0;
-    sfor<1, NQ>([&](auto ic) { any |= bmask(ic); });
-    any = uniform_u64(any);
 
-    const long long sb = g.S * (long long)sizeof(T);
     char* base = (char*)f;
     const uint32_t off = (uint32_t)((long long)x + (long long)g.pitch * row) * (uint32_t)sizeof(T);
     R h[NQ];
-    if (any == 0) {
+    if (!solid_any && !x_lo && !x_hi) {
         // fast path: no solid neighbour, no face lane
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            constexpr V3 c = dirv(I);
-            const long long d = (long long)c.x + (long long)g.pitch * (c.y + (long long)g.ny * c.z);
-            const char* sbI = base + opp(I) * sb - d * (long long)sizeof(T);
-            h[I] = C::raw(ld_pop((const T*)(sbI + off)));
+            h[I] = C::raw(ld_pop((const T*)(base + O.odd[I] + off)));
         });
         R drho, ux, uy, uz, tau;
         collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            constexpr V3 c = dirv(I);
-            const long long d = (long long)c.x + (long long)g.pitch * (c.y + (long long)g.ny * c.z);
-            char* sbI = base + opp(I) * sb - d * (long long)sizeof(T);
-            st_pop((T*)(sbI + off), C::pack(h[opp(I)]));
+            st_pop((T*)(base + O.odd[I] + off), C::pack(h[opp(I)]));
         });
         if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
         return;
@@ -209,18 +220,12 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
         if constexpr (I == 0) {
             so[0] = off;
         } else {
-            constexpr V3 c = dirv(I);
-            constexpr int lo = I < opp(I) ? I : opp(I);
-            const long long d = (long long)c.x + (long long)g.pitch * (c.y + (long long)g.ny * c.z);
-            const uint32_t on = off + (uint32_t)((opp(I) - lo) * sb - d * (long long)sizeof(T));
-            const uint32_t oo = off + (uint32_t)((I - lo) * sb);
-            so[I] = lane_select(on, oo, bmask(ic));
+            so[I] = lane_select(off + O.on[I], off + O.oo[I], bmask(ic));
         }
     });
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        constexpr int lo = I < opp(I) ? I : opp(I);
-        h[I] = C::raw(ld_pop((const T*)(base + lo * sb + so[I])));
+        h[I] = C::raw(ld_pop((const T*)(base + O.lo[I] + so[I])));
     });
     const bool inflow_lane = x_lo && g.face[0] == F_INFLOW && lane == 0;
     const bool outflow_lane = x_hi && g.face[1] == F_OUTFLOW && lane == l_out;
@@ -247,8 +252,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
     }
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        constexpr int lo = I < opp(I) ? I : opp(I);
-        st_pop((T*)(base + lo * sb + so[I]), C::pack(h[opp(I)]));
+        st_pop((T*)(base + O.lo[I] + so[I]), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
 }
@@ -263,7 +267,8 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const doub
 template <int K>
 __global__ void __launch_bounds__(256)
 k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::store* __restrict__ dst,
-       const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P, long long nwaves)
+       const uint64_t* __restrict__ mask, const int* __restrict__ wave_idx, const uint64_t* __restrict__ wave_tab,
+       Geo g, Phys<typename Codec<K>::real> P, StepOff O, long long nwaves)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -277,36 +282,30 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     const Box B = main_box(g, 0);
     if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
     const int x = cx * 64 + lane;
-    RowWin W;
-    load_rows(W, mask, g, cx, y, z);
+    const WaveMask WM = wave_mask(wave_idx, wave_tab, wave);
+    const uint64_t own = mask_word(mask, row * g.wpr + cx);
     if (x < B.x0 || x > B.x1) return;
-    const long long sb = g.N * (long long)sizeof(T);
     const uint32_t off = (uint32_t)((long long)x + (long long)g.nx * row) * (uint32_t)sizeof(T);
     const char* sbase = (const char*)src;
     char* dbase = (char*)dst;
-    if ((W.c[1][1] >> lane) & 1ull) {
+    if ((own >> lane) & 1ull) {
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            st_pop((T*)(dbase + I * sb + off), C::pack(R(0)));
+            st_pop((T*)(dbase + O.even[I] + off), C::pack(R(0)));
         });
         return;
     }
-    uint64_t any = 0;
-    sfor<1, NQ>([&](auto ic) { any |= solid_src_mask<decltype(ic)::value>(W); });
-    any = uniform_u64(any);
     R h[NQ];
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        h[I] = C::raw(ld_pop((const T*)(sbase + I * sb + off)));
+        h[I] = C::raw(ld_pop((const T*)(sbase + O.even[I] + off)));
     });
     R drho, ux, uy, uz, tau;
     collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
-    if (any == 0) {
+    if (!WM.m) {
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            constexpr V3 c = dirv(I);
-            const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
-            st_pop((T*)(dbase + opp(I) * sb - d * (long long)sizeof(T) + off), C::pack(h[opp(I)]));
+            st_pop((T*)(dbase + O.odd[I] + off), C::pack(h[opp(I)]));
         });
         return;
     }
@@ -315,13 +314,8 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
         if constexpr (I == 0) {
             st_pop((T*)(dbase + off), C::pack(h[0]));
         } else {
-            constexpr V3 c = dirv(I);
-            constexpr int lo = I < opp(I) ? I : opp(I);
-            const long long d = (long long)c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
-            const uint32_t on = off + (uint32_t)((opp(I) - lo) * sb - d * (long long)sizeof(T));
-            const uint32_t oo = off + (uint32_t)((I - lo) * sb);
-            const uint32_t so = lane_select(on, oo, solid_src_mask<I>(W));
-            st_pop((T*)(dbase + lo * sb + so), C::pack(h[opp(I)]));
+            const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], WM.template get<I>());
+            st_pop((T*)(dbase + O.lo[I] + so), C::pack(h[opp(I)]));
         }
     });
 }
@@ -336,23 +330,24 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
     const Phys<R> P = phys_of<K>(d);
+    const StepOff O = step_offsets<typename C::store>(d.g.S, d.g.pitch, d.g.ny);
     auto* f = (typename C::store*)d.f;
     if (!odd) {
         if (stats)
-            hipLaunchKernelGGL((k_even<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P,
+            hipLaunchKernelGGL((k_even<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P, O,
                                (R*)stats, nwaves, nbp);
         else
-            hipLaunchKernelGGL((k_even<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P,
+            hipLaunchKernelGGL((k_even<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P, O,
                                (R*)stats, nwaves, nbp);
         return hipGetLastError();
     }
     const auto* gh = (const typename C::store*)d.ghost;
     if (stats)
-        hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, gh, d.g, P,
-                           (R*)stats, nwaves, nbp);
+        hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx, d.wave_tab,
+                           d.uin, gh, d.g, P, O, (R*)stats, nwaves, nbp);
     else
-        hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, gh, d.g, P,
-                           (R*)stats, nwaves, nbp);
+        hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx, d.wave_tab,
+                           d.uin, gh, d.g, P, O, (R*)stats, nwaves, nbp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_general_odd(d, stats, s);
@@ -363,8 +358,10 @@ static hipError_t launch_push_k(const DevCtx& d, const void* src, void* dst, hip
 {
     using C = Codec<K>;
     const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
+    const StepOff O = step_offsets<typename C::store>(d.g.N, d.g.nx, d.g.ny);
     hipLaunchKernelGGL((k_push<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
-                       (const typename C::store*)src, (typename C::store*)dst, d.mask, d.g, phys_of<K>(d), nwaves);
+                       (const typename C::store*)src, (typename C::store*)dst, d.mask, d.wave_idx, d.wave_tab, d.g,
+                       phys_of<K>(d), O, nwaves);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = launch_push_cells(d, src, dst, s)) != hipSuccess) return e;
