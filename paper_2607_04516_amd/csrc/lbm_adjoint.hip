@@ -91,30 +91,34 @@ __device__ inline R adj_gather(const R* lam_next, const uint64_t* __restrict__ m
 }
 
 // mu = J_C(h)^T ls for one cell (h shifted populations, in place into ls).
+//
+// Every sum over directions that the transpose needs is a low moment of the
+// adjoint populations: with the pair sums a_k = ls_+ + ls_- and differences
+// b_k = ls_+ - ls_- of the nine opposite pairs, the weighted moments
+// S0 = sum w ls, S_a = sum w ls c_a and S_ab = sum w ls c_a c_b give
+//   A   = sum ls feq / rho = S0 (1 - 3/2 u.u) + 3 S.u + 9/2 u.S2.u,
+//   V_a = rho (3 S_a + 9 (S2 u)_a - 3 u_a S0)        (feq's u-derivative),
+//   E_a = -3 F_a S0 + 9 (S2 F)_a,  P = 3 S.F - 3 u.F S0 + 9 u.S2.F  (Guo),
+// and G = sum ls (h - heq) = sum ls h - rho A + rho0 S0.  Pi comes from the
+// second moment of h as in the forward collision.  The result per pair is
+// an even part (shared) plus or minus an odd part.
 template <typename R>
 __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
 {
-    R drho, ux, uy, uz, inv_rho, Fx, Fy, Fz;
+    R drho, ux, uy, uz, Fx, Fy, Fz;
     moments_pairs<R, 1>(h, P, drho, ux, uy, uz, Fx, Fy, Fz);
-    inv_rho = fast_rcp<R>(P.rho0 + drho);
     const R rho = P.rho0 + drho;
-    R heq[NQ];
-    equilibrium_shifted<R>(rho, drho, ux, uy, uz, heq);
-    // non-equilibrium flux and closure
-    R neq[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; i++) neq[i] = h[i] - heq[i];
-    R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-#pragma unroll
-    for (int i = 0; i < NQ; i++) {
-        const V3 c = dirv(i);
-        pxx += R(c.x * c.x) * neq[i];
-        pyy += R(c.y * c.y) * neq[i];
-        pzz += R(c.z * c.z) * neq[i];
-        pxy += R(c.x * c.y) * neq[i];
-        pxz += R(c.x * c.z) * neq[i];
-        pyz += R(c.y * c.z) * neq[i];
-    }
+    const R inv_rho = R(1) / rho;
+    // non-equilibrium second moment Pi = M - drho/3 I - rho u u
+    const R s1 = h[1] + h[2], s2 = h[3] + h[4], s3 = h[5] + h[6], s4 = h[7] + h[8], s5 = h[9] + h[10];
+    const R s6 = h[11] + h[12], s7 = h[13] + h[14], s8 = h[15] + h[16], s9 = h[17] + h[18];
+    const R t3 = drho * R(1.0 / 3.0);
+    const R pxx = (((s1 + s4) + (s5 + s7)) + s8) - t3 - rho * ux * ux;
+    const R pyy = (((s2 + s4) + (s6 + s7)) + s9) - t3 - rho * uy * uy;
+    const R pzz = (((s3 + s5) + (s6 + s8)) + s9) - t3 - rho * uz * uz;
+    const R pxy = (s4 - s7) - rho * ux * uy;
+    const R pxz = (s5 - s8) - rho * ux * uz;
+    const R pyz = (s6 - s9) - rho * uy * uz;
     const R pp = (pxx * pxx + pyy * pyy + pzz * pzz) + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
     const R q = sqrt(R(2) * pp);
     const R D = P.tau0 * P.tau0 + P.ksmag * q * inv_rho;
@@ -122,47 +126,48 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
     const R tau = R(0.5) * (P.tau0 + sD);
     const R omega = R(1) / tau;
 
-    // reductions over lam*
-    R A = 0, G = 0, Pw = 0;              // sum ls feq/rho, sum ls neq, sum ls w B
-    R s0 = 0, sx = 0, sy = 0, sz = 0;    // sum w ls, sum w ls c
-    R tx = 0, ty = 0, tz = 0;            // sum w ls (c.u) c
-    R ex = 0, ey = 0, ez = 0;            // sum w ls c (c.F)
+    // moments of the adjoint populations
+    constexpr R w0 = R(1.0 / 3.0), wf = R(1.0 / 18.0), we = R(1.0 / 36.0);
+    R a[10], b[10];
 #pragma unroll
-    for (int i = 0; i < NQ; i++) {
-        const V3 c = dirv(i);
-        const R w = weight<R>(i);
-        const R l = ls[i];
-        const R e = R(c.x) * ux + R(c.y) * uy + R(c.z) * uz;
-        A += l * (heq[i] + w * P.rho0);
-        G += l * neq[i];
-        const R wl = w * l;
-        s0 += wl;
-        sx += R(c.x) * wl;
-        sy += R(c.y) * wl;
-        sz += R(c.z) * wl;
-        tx += R(c.x) * e * wl;
-        ty += R(c.y) * e * wl;
-        tz += R(c.z) * e * wl;
-        if (P.has_force) {
-            const R cF = R(c.x) * Fx + R(c.y) * Fy + R(c.z) * Fz;
-            const R uF = ux * Fx + uy * Fy + uz * Fz;
-            Pw += wl * (R(3) * (cF - uF) + R(9) * e * cF);
-            ex += R(c.x) * cF * wl;
-            ey += R(c.y) * cF * wl;
-            ez += R(c.z) * cF * wl;
-        }
+    for (int k = 1; k <= 9; k++) {
+        a[k] = ls[2 * k - 1] + ls[2 * k];
+        b[k] = ls[2 * k - 1] - ls[2 * k];
     }
-    A *= inv_rho;
-    // V_a = rho (3 sum w l c_a + 9 sum w l e c_a - 3 u_a sum w l);  E_a = -3 F_a sum w l + 9 sum w l c_a (c.F)
-    const R vx = rho * (R(3) * sx + R(9) * tx - R(3) * ux * s0);
-    const R vy = rho * (R(3) * sy + R(9) * ty - R(3) * uy * s0);
-    const R vz = rho * (R(3) * sz + R(9) * tz - R(3) * uz * s0);
+    R Lh = ls[0] * h[0];
+#pragma unroll
+    for (int i = 1; i < NQ; i++) Lh += ls[i] * h[i];
+    const R S0 = w0 * ls[0] + wf * ((a[1] + a[2]) + a[3]) + we * (((a[4] + a[5]) + (a[6] + a[7])) + (a[8] + a[9]));
+    const R Sx = wf * b[1] + we * ((b[4] + b[5]) + (b[7] + b[8]));
+    const R Sy = wf * b[2] + we * ((b[4] + b[6]) + (b[9] - b[7]));
+    const R Sz = wf * b[3] + we * ((b[5] + b[6]) - (b[8] + b[9]));
+    const R Sxx = wf * a[1] + we * ((a[4] + a[5]) + (a[7] + a[8]));
+    const R Syy = wf * a[2] + we * ((a[4] + a[6]) + (a[7] + a[9]));
+    const R Szz = wf * a[3] + we * ((a[5] + a[6]) + (a[8] + a[9]));
+    const R Sxy = we * (a[4] - a[7]), Sxz = we * (a[5] - a[8]), Syz = we * (a[6] - a[9]);
+    // S2 u and S2 F
+    const R tx = Sxx * ux + Sxy * uy + Sxz * uz;
+    const R ty = Sxy * ux + Syy * uy + Syz * uz;
+    const R tz = Sxz * ux + Syz * uy + Szz * uz;
+    const R usq = ux * ux + uy * uy + uz * uz;
+    const R A = S0 * (R(1) - R(1.5) * usq) + R(3) * (Sx * ux + Sy * uy + Sz * uz) +
+                R(4.5) * (ux * tx + uy * ty + uz * tz);
+    const R G = Lh - rho * A + P.rho0 * S0;
+    const R vx = rho * (R(3) * Sx + R(9) * tx - R(3) * ux * S0);
+    const R vy = rho * (R(3) * Sy + R(9) * ty - R(3) * uy * S0);
+    const R vz = rho * (R(3) * Sz + R(9) * tz - R(3) * uz * S0);
     R Wx = omega * vx, Wy = omega * vy, Wz = omega * vz;
+    R Pw = R(0);
     if (P.has_force) {
+        const R ex = Sxx * Fx + Sxy * Fy + Sxz * Fz;
+        const R ey = Sxy * Fx + Syy * Fy + Syz * Fz;
+        const R ez = Sxz * Fx + Syz * Fy + Szz * Fz;
+        const R uF = ux * Fx + uy * Fy + uz * Fz;
+        Pw = R(3) * (Sx * Fx + Sy * Fy + Sz * Fz) - R(3) * uF * S0 + R(9) * (ux * ex + uy * ey + uz * ez);
         const R pre = R(1) - R(0.5) * omega;
-        Wx += pre * (R(-3) * Fx * s0 + R(9) * ex);
-        Wy += pre * (R(-3) * Fy * s0 + R(9) * ey);
-        Wz += pre * (R(-3) * Fz * s0 + R(9) * ez);
+        Wx += pre * (R(-3) * Fx * S0 + R(9) * ex);
+        Wy += pre * (R(-3) * Fy * S0 + R(9) * ey);
+        Wz += pre * (R(-3) * Fz * S0 + R(9) * ez);
     }
     Wx *= inv_rho;
     Wy *= inv_rho;
@@ -182,18 +187,19 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
         Wy = ay;
         Wz = az;
     }
-    // closure: -(d omega/d f_j)(G + P/2) = Z (dQ_j - Q/rho)
-    R Z = R(0), twoq = R(0), base = R(0);
+    // closure: -(d omega/d f_j)(G + P/2) = Z (dQ_j - Q/rho),
+    // dQ_j = (2/Q)[c.Pi.c - 2 (M c).Pi u + u.Pi.u - tr(Pi)/3]
+    R Zt = R(0), base = R(0), Zq = R(0);
     R pux = 0, puy = 0, puz = 0;
     if (P.ksmag > R(0) && q > R(0)) {
-        Z = (G + R(0.5) * Pw) * omega * omega * P.ksmag / (R(4) * sD) * inv_rho;
-        twoq = R(2) / q;
+        const R Z = (G + R(0.5) * Pw) * omega * omega * P.ksmag / (R(4) * sD) * inv_rho;
+        Zt = Z * (R(2) / q);
+        Zq = Z * q * inv_rho;
         pux = pxx * ux + pxy * uy + pxz * uz;
         puy = pxy * ux + pyy * uy + pyz * uz;
         puz = pxz * ux + pyz * uy + pzz * uz;
-        const R upu = ux * pux + uy * puy + uz * puz;
-        base = upu - (pxx + pyy + pzz) / R(3);   // dQ_j = (2/Q)[c.Pi.c - 2 (M c).Pi u + base]
-        if (P.has_rot) {                         // (M c).Pi u = c . M^T (Pi u)
+        base = (ux * pux + uy * puy + uz * puz) - (pxx + pyy + pzz) / R(3);
+        if (P.has_rot) {   // (M c).Pi u = c . M^T (Pi u)
             const R ax = pux + R(0.5) * (W2[1] * puz - W2[2] * puy);
             const R ay = puy + R(0.5) * (W2[2] * pux - W2[0] * puz);
             const R az = puz + R(0.5) * (W2[0] * puy - W2[1] * pux);
@@ -202,22 +208,27 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
             puz = az;
         }
     }
-    const R Zq = Z * q * inv_rho;
-    const R omA = omega * A;
     const R om1 = R(1) - omega;
-#pragma unroll
-    for (int j = 0; j < NQ; j++) {
-        const V3 c = dirv(j);
-        R mu = om1 * ls[j] + omA + (R(c.x) * Wx + R(c.y) * Wy + R(c.z) * Wz) - Wu;
-        if (P.ksmag > R(0)) {
-            const R cpc = R(c.x * c.x) * pxx + R(c.y * c.y) * pyy + R(c.z * c.z) * pzz +
-                          R(2) * (R(c.x * c.y) * pxy + R(c.x * c.z) * pxz + R(c.y * c.z) * pyz);
-            const R cpu = R(c.x) * pux + R(c.y) * puy + R(c.z) * puz;
-            const R dq = twoq * (cpc - R(2) * cpu + base);
-            mu += Z * dq - Zq;
-        }
-        ls[j] = mu;
+    const R e0 = omega * A - Wu + Zt * base - Zq;   // the c-independent part of every mu_j
+    ls[0] = om1 * ls[0] + e0;
+    // pair k (directions 2k-1 = +c and 2k = -c): mu = om1 ls + even +- odd
+#define LBM_ADJ_PAIR(k, cpc, cw, cpu)                          \
+    {                                                          \
+        const R ev = e0 + Zt * (cpc);                          \
+        const R od = (cw) - R(2) * Zt * (cpu);                 \
+        ls[2 * (k) - 1] = om1 * ls[2 * (k) - 1] + (ev + od);   \
+        ls[2 * (k)] = om1 * ls[2 * (k)] + (ev - od);           \
     }
+    LBM_ADJ_PAIR(1, pxx, Wx, pux)
+    LBM_ADJ_PAIR(2, pyy, Wy, puy)
+    LBM_ADJ_PAIR(3, pzz, Wz, puz)
+    LBM_ADJ_PAIR(4, pxx + pyy + R(2) * pxy, Wx + Wy, pux + puy)
+    LBM_ADJ_PAIR(5, pxx + pzz + R(2) * pxz, Wx + Wz, pux + puz)
+    LBM_ADJ_PAIR(6, pyy + pzz + R(2) * pyz, Wy + Wz, puy + puz)
+    LBM_ADJ_PAIR(7, pxx + pyy - R(2) * pxy, Wx - Wy, pux - puy)
+    LBM_ADJ_PAIR(8, pxx + pzz - R(2) * pxz, Wx - Wz, pux - puz)
+    LBM_ADJ_PAIR(9, pyy + pzz - R(2) * pyz, Wy - Wz, puy - puz)
+#undef LBM_ADJ_PAIR
 }
 
 // Adjoint of one cell on the general path (every boundary rule).
