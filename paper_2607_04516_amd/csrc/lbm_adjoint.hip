@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(256)
 k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
                typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
                const int* __restrict__ wave_idx, const uint64_t* __restrict__ wave_tab, Geo g,
-               Phys<typename Codec<K>::real> P, StepOff O, long long nwaves)
+               Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab, long long nwaves)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -297,6 +297,7 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
     const Box B = main_box(g, 1);
     if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
     const int x = cx * 64 + lane;
+    const auto& O = class_offsets(otab, row_class(g, y, z));
     const WaveMask WM = wave_mask(wave_idx, wave_tab, wave);
     const uint64_t own = mask_word(mask, row * g.wpr + cx);
     if (x < B.x0 || x > B.x1) return;
@@ -482,10 +483,9 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
         }
     }
     const long long nwaves = (long long)g.ncx * g.ny * g.nz;
-    const StepOff O = step_offsets<R>(g.N, g.nx, g.ny);
     hipLaunchKernelGGL((k_adjoint_main<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
                        (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, d.wave_idx, d.wave_tab, g,
-                       P, O, nwaves);
+                       P, d.off_adj, nwaves);
     if (d.adj_list_n > 0)
         hipLaunchKernelGGL((k_adjoint_cells<K>), dim3((unsigned)((d.adj_list_n + 255) / 256)), dim3(256), 0, s,
                            (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,

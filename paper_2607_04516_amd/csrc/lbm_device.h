@@ -667,11 +667,17 @@ __device__ inline void load_rows(RowWin& W, const uint64_t* mask, const Geo& g, 
     // Every word is computed as a value (loads from a clamped, always valid
     // index, then selects), never stored under a branch: that keeps the
     // window in scalar registers instead of a private (scratch) array.
+    // A row beyond a FREESLIP face is the face row itself (the mirrored pull
+    // source lies in the cell's own row); beyond a WALL face it is all solid.
 #pragma unroll
     for (int dz = -1; dz <= 1; dz++)
 #pragma unroll
         for (int dy = -1; dy <= 1; dy++) {
-            const int yy = y + dy, zz = z + dz;
+            int yy = y + dy, zz = z + dz;
+            if (yy < 0 && g.face[2] == F_FREESLIP) yy = 0;
+            if (yy >= g.ny && g.face[3] == F_FREESLIP) yy = g.ny - 1;
+            if (zz < 0 && g.face[4] == F_FREESLIP) zz = 0;
+            if (zz >= g.nz && g.face[5] == F_FREESLIP) zz = g.nz - 1;
             const bool out = yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz;
             const long long w = out ? (long long)cx : ((long long)yy + (long long)g.ny * zz) * g.wpr + cx;
             const uint64_t wc = mask_word(mask, w);
@@ -685,18 +691,31 @@ __device__ inline void load_rows(RowWin& W, const uint64_t* mask, const Geo& g, 
 
 // The box of cells the fast kernels take (inclusive bounds): every cell at
 // least L layers inside each face, L = 0 for WALL faces (bounce-back, like
-// solid cells), 1 for FREESLIP and PERIODIC faces (their pulls remap), and
-// 1 (push) or 2 (adjoint: outflow copies and inflow cells reach one layer
-// further) for INFLOW and OUTFLOW faces.  The rest runs the general code.
+// solid cells) and FREESLIP faces (a per-row remap of the crossing
+// directions, see row_class), 1 for PERIODIC faces, and 1 (push) or 2
+// (adjoint: outflow copies and inflow cells reach one layer further) for
+// INFLOW and OUTFLOW faces.  The rest runs the general code.
 struct Box {
     int x0, x1, y0, y1, z0, z1;
 };
 
 __host__ __device__ inline int face_layers(int kind, int adjoint)
 {
-    if (kind == F_WALL) return 0;
+    if (kind == F_WALL || kind == F_FREESLIP) return 0;
     if (kind == F_INFLOW || kind == F_OUTFLOW) return adjoint ? 2 : 1;
     return 1;
+}
+
+// Row class of the fast kernels: 3 cy + cz with cy = 1 (2) for the y = 0
+// (y = ny - 1) row of a FREESLIP face, else 0, and cz likewise for z.  In
+// such a row every direction that crosses the face pulls the mirrored
+// direction from the neighbour in the cell's own row (specular reflection at
+// the face plane), a wave-uniform change of slot and offset.
+__host__ __device__ inline int row_class(const Geo& g, int y, int z)
+{
+    const int cy = (y == 0 && g.face[2] == F_FREESLIP) ? 1 : ((y == g.ny - 1 && g.face[3] == F_FREESLIP) ? 2 : 0);
+    const int cz = (z == 0 && g.face[4] == F_FREESLIP) ? 1 : ((z == g.nz - 1 && g.face[5] == F_FREESLIP) ? 2 : 0);
+    return 3 * cy + cz;
 }
 
 __host__ __device__ inline Box main_box(const Geo& g, int adjoint)

@@ -8,6 +8,8 @@
 
 namespace lbm {
 
+struct StepOff;
+
 // Everything a kernel launch needs to know about one context.
 struct DevCtx {
     Geo g;
@@ -25,6 +27,9 @@ struct DevCtx {
     long long adj_list_n;
     const int* wave_idx;       // per wave (chunk, row): entry in wave_tab, -1 without solid neighbour
     const uint64_t* wave_tab;  // [entries][18] solid-source masks
+    const StepOff* off_odd;    // [9] row-class offsets, padded layout, store elements
+    const StepOff* off_push;   // [9] canonical layout, store elements
+    const StepOff* off_adj;    // [9] canonical layout, real (adjoint) elements
     double tau0, c_smag, delta, rho0, force[3];
     double omega[3];      // rotation vector in lattice units (Coriolis); zero: none
     int sponge_w;         // sponge / buffer layer width; 0: off
@@ -52,45 +57,62 @@ static inline Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
     return P;
 }
 
-// Byte offsets of the population slots a wave touches, fixed per grid and
-// codec and computed once per launch on the host (otherwise every wave
-// rebuilds them with 64-bit scalar arithmetic).  Slice stride sb = S (padded
-// in-place layout) or N (canonical layout) times the store size; d_I is the
-// element offset of the neighbour x + c_I.
+// Byte offsets of the population slots a wave touches, fixed per grid,
+// codec and row class, computed on the host (otherwise every wave rebuilds
+// them with 64-bit scalar arithmetic).  Slice stride sb = S (padded in-place
+// layout) or N (canonical layout) times the element size; the pull of
+// direction I reads slot opp(I') of the source cell x - c', where I' and c'
+// are I and c_I with the components mirrored at FREESLIP faces (row_class)
+// flipped and zeroed; d_I is the element offset of x - c'.
 struct StepOff {
     long long even[NQ];  // I sb: slot I of the own cell
-    long long odd[NQ];   // opp(I) sb - d_I: slot opp(I) of the neighbour x - c_I
-    long long lo[NQ];    // min(I, opp(I)) sb
-    uint32_t on[NQ];     // (opp(I) - lo) sb - d_I, relative to lo (mod 2^32)
-    uint32_t oo[NQ];     // (I - lo) sb
+    long long odd[NQ];   // opp(I') sb - d_I: the pull source of direction I
+    long long lo[NQ];    // min(I, opp(I')) sb
+    uint32_t on[NQ];     // (opp(I') - lo) sb - d_I, relative to lo (mod 2^32)
+    uint32_t oo[NQ];     // (I - lo) sb: the own slot (bounce-back)
 };
 
-template <typename T>
-static StepOff step_offsets(long long slice, long long rowlen, long long ny)
+static inline StepOff step_offsets(long long slice, long long rowlen, long long ny, int elem, int cls = 0)
 {
     StepOff o;
-    const long long sb = slice * (long long)sizeof(T);
+    const long long sb = slice * (long long)elem;
+    const int my = cls / 3, mz = cls % 3;
     for (int i = 0; i < NQ; i++) {
         const V3 c = dirv(i);
-        const int lo = i < opp(i) ? i : opp(i);
-        const long long d = ((long long)c.x + rowlen * (c.y + ny * c.z)) * (long long)sizeof(T);
+        int m = 0;
+        if ((my == 1 && c.y == 1) || (my == 2 && c.y == -1)) m |= 2;
+        if ((mz == 1 && c.z == 1) || (mz == 2 && c.z == -1)) m |= 4;
+        const int slot = opp(mirrored(i, m));
+        const int lo = i < slot ? i : slot;
+        const long long d =
+            ((long long)c.x + rowlen * ((m & 2 ? 0 : c.y) + ny * (m & 4 ? 0 : c.z))) * (long long)elem;
         o.even[i] = i * sb;
-        o.odd[i] = opp(i) * sb - d;
+        o.odd[i] = slot * sb - d;
         o.lo[i] = lo * sb;
-        o.on[i] = (uint32_t)((opp(i) - lo) * sb - d);
+        o.on[i] = (uint32_t)((slot - lo) * sb - d);
         o.oo[i] = (uint32_t)((i - lo) * sb);
     }
     return o;
 }
 
+typedef const StepOff __attribute__((address_space(4))) const_stepoff;
+
+// The offsets of one row class from a per-context table of nine.
+__device__ inline const const_stepoff& class_offsets(const StepOff* tab, int cls)
+{
+    return ((const const_stepoff*)tab)[cls];
+}
+
 // Host copy of the odd kernel's test for waves it leaves to the general
 // kernel (k_odd in lbm_step.hip applies the same test).
-// Rows on a y or z face other than WALL, and chunks holding an x-face cell
-// unless the x- face is INFLOW or WALL and the x+ face OUTFLOW or WALL.
+// Rows on a y or z face other than WALL or FREESLIP, and chunks holding an
+// x-face cell unless the x- face is INFLOW or WALL and the x+ face OUTFLOW
+// or WALL.
 __host__ __device__ inline bool odd_wave_is_general(const Geo& g, int cx, int y, int z)
 {
-    if ((y == 0 && g.face[2] != F_WALL) || (y == g.ny - 1 && g.face[3] != F_WALL)) return true;
-    if ((z == 0 && g.face[4] != F_WALL) || (z == g.nz - 1 && g.face[5] != F_WALL)) return true;
+    auto folded = [](int kind) { return kind == F_WALL || kind == F_FREESLIP; };
+    if ((y == 0 && !folded(g.face[2])) || (y == g.ny - 1 && !folded(g.face[3]))) return true;
+    if ((z == 0 && !folded(g.face[4])) || (z == g.nz - 1 && !folded(g.face[5]))) return true;
     if (cx == 0 && g.face[0] != F_INFLOW && g.face[0] != F_WALL) return true;
     if (cx * 64 + 63 >= g.nx - 1 && g.face[1] != F_OUTFLOW && g.face[1] != F_WALL) return true;
     return false;

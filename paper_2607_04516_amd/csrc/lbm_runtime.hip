@@ -49,6 +49,7 @@ struct lbm_ctx {
     unsigned* odd_list = nullptr;
     unsigned* push_list = nullptr;
     unsigned* adj_list = nullptr;
+    StepOff* offsets = nullptr;     // [27] row-class slot offsets: odd, push, adjoint
     int* wave_idx = nullptr;        // per wave: entry in wave_tab or -1
     uint64_t* wave_tab = nullptr;   // solid-source masks of waves with a solid neighbour
     void* stats = nullptr;
@@ -108,7 +109,7 @@ static void free_all(lbm_ctx* c)
     vk_destroy(c->vk);
     c->vk = nullptr;
     void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
-                    c->push_list, c->adj_list, c->uin, c->flux_cells, c->flux_red, c->wave_idx, c->wave_tab};
+                    c->push_list, c->adj_list, c->uin, c->flux_cells, c->flux_red, c->wave_idx, c->wave_tab, c->offsets};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -128,6 +129,7 @@ static void free_all(lbm_ctx* c)
     c->n_flux = -1;
     c->wave_idx = nullptr;
     c->wave_tab = nullptr;
+    c->offsets = nullptr;
 }
 
 
@@ -165,6 +167,21 @@ static int build_wave_masks(lbm_ctx* c)
     HIPCHK(c, hipStreamSynchronize(c->stream), "wave mask table");
     c->d.wave_idx = c->wave_idx;
     c->d.wave_tab = c->wave_tab;
+    // slot offsets of the nine row classes for the odd step (padded layout),
+    // the push recompute and the adjoint (canonical layout)
+    std::vector<StepOff> off(27);
+    const int es = (int)c->store_bytes, er = c->p.storage == LBM_F64 ? 8 : 4;
+    for (int k = 0; k < 9; k++) {
+        off[k] = step_offsets(g.S, g.pitch, g.ny, es, k);
+        off[9 + k] = step_offsets(g.N, g.nx, g.ny, es, k);
+        off[18 + k] = step_offsets(g.N, g.nx, g.ny, er, k);
+    }
+    if ((rc = device_alloc(c, (void**)&c->offsets, off.size() * sizeof(StepOff), "slot offsets")) != LBM_OK)
+        return rc;
+    HIPCHK(c, hipMemcpy(c->offsets, off.data(), off.size() * sizeof(StepOff), hipMemcpyHostToDevice), "slot offsets");
+    c->d.off_odd = c->offsets;
+    c->d.off_push = c->offsets + 9;
+    c->d.off_adj = c->offsets + 18;
     return LBM_OK;
 }
 

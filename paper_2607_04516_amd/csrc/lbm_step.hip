@@ -139,8 +139,8 @@ template <int K, bool STATS>
 __global__ void __launch_bounds__(256)
 k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int* __restrict__ wave_idx,
       const uint64_t* __restrict__ wave_tab, const double* __restrict__ uin,
-      const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P, StepOff O,
-      typename Codec<K>::real* stats, long long nwaves, long long nbp)
+      const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P,
+      const StepOff* __restrict__ otab, typename Codec<K>::real* stats, long long nwaves, long long nbp)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -153,6 +153,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
     const int y = (int)(row % g.ny), z = (int)(row / g.ny);
     if (odd_general_wave(g, cx, y, z)) return;
     const int x = cx * 64 + lane;
+    const auto& O = class_offsets(otab, row_class(g, y, z));
     const bool x_lo = (cx == 0);                   // lane 0 is an x- inflow or wall cell
     const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane l_out is an x+ outflow or wall cell
     const int l_out = (g.nx - 1) - cx * 64;
@@ -268,7 +269,7 @@ template <int K>
 __global__ void __launch_bounds__(256)
 k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::store* __restrict__ dst,
        const uint64_t* __restrict__ mask, const int* __restrict__ wave_idx, const uint64_t* __restrict__ wave_tab,
-       Geo g, Phys<typename Codec<K>::real> P, StepOff O, long long nwaves)
+       Geo g, Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab, long long nwaves)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -282,6 +283,7 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     const Box B = main_box(g, 0);
     if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
     const int x = cx * 64 + lane;
+    const auto& O = class_offsets(otab, row_class(g, y, z));
     const WaveMask WM = wave_mask(wave_idx, wave_tab, wave);
     const uint64_t own = mask_word(mask, row * g.wpr + cx);
     if (x < B.x0 || x > B.x1) return;
@@ -330,7 +332,7 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
     const Phys<R> P = phys_of<K>(d);
-    const StepOff O = step_offsets<typename C::store>(d.g.S, d.g.pitch, d.g.ny);
+    const StepOff O = step_offsets(d.g.S, d.g.pitch, d.g.ny, (int)sizeof(typename C::store));
     auto* f = (typename C::store*)d.f;
     if (!odd) {
         if (stats)
@@ -344,10 +346,10 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     const auto* gh = (const typename C::store*)d.ghost;
     if (stats)
         hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx, d.wave_tab,
-                           d.uin, gh, d.g, P, O, (R*)stats, nwaves, nbp);
+                           d.uin, gh, d.g, P, d.off_odd, (R*)stats, nwaves, nbp);
     else
         hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx, d.wave_tab,
-                           d.uin, gh, d.g, P, O, (R*)stats, nwaves, nbp);
+                           d.uin, gh, d.g, P, d.off_odd, (R*)stats, nwaves, nbp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_general_odd(d, stats, s);
@@ -358,10 +360,9 @@ static hipError_t launch_push_k(const DevCtx& d, const void* src, void* dst, hip
 {
     using C = Codec<K>;
     const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
-    const StepOff O = step_offsets<typename C::store>(d.g.N, d.g.nx, d.g.ny);
     hipLaunchKernelGGL((k_push<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
                        (const typename C::store*)src, (typename C::store*)dst, d.mask, d.wave_idx, d.wave_tab, d.g,
-                       phys_of<K>(d), O, nwaves);
+                       phys_of<K>(d), d.off_push, nwaves);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = launch_push_cells(d, src, dst, s)) != hipSuccess) return e;

@@ -66,6 +66,29 @@ def test_adjoint_step_f64_matches_oracle(fi, dims):
     assert np.abs(g_g - g_o).max() <= 1e-12 * gs
 
 
+def test_adjoint_step_freeslip_rows_multichunk_f64():
+    """Free-slip face rows in the fast adjoint kernel, several chunks, solids in the face rows."""
+    nx, ny, nz = 140, 7, 6
+    rng = np.random.default_rng(11)
+    solid = (rng.random((nz, ny, nx)) < 0.05).astype(np.uint8)
+    for x in (5, 63, 64, 100, 127, 128):
+        solid[2, 0, x] = solid[3, ny - 1, x] = solid[nz - 1, 3, x] = 1
+    solid[:, :, :3] = 0
+    solid[:, :, nx - 3:] = 0
+    w = small_workload(nx, ny, nz, ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip"),
+                       solid=solid, tau0=0.53, c_smag=0.15, u=(0.05, 0.02, 0.01), noise=5e-3, seed=9)
+    o = oracle_for(w)
+    f = o.run(oracle_init(o, w), 3)
+    m = fluid_mask(w)
+    lam_next = rng.standard_normal(f.shape) * m[None]
+    probes = np.argwhere(m)[:: max(1, m.sum() // 5)][:5][:, ::-1].astype(np.int32)
+    src = rng.standard_normal((len(probes), 3))
+    lam_o, g_o = o.adjoint_step(f, lam_next, probes, src)
+    lam_g, g_g = _gpu_adjoint(w, f, lam_next, probes, src)
+    assert np.abs(lam_g - lam_o).max() <= 1e-12 * np.abs(lam_o).max()
+    assert np.abs(g_g - g_o).max() <= 1e-12 * np.abs(g_o).max()
+
+
 def test_adjoint_step_force_f64():
     w, o, f, lam_next, probes, src = _problem(0, (9, 6, 5), "f64", force=(2e-5, -1e-5, 3e-6))
     lam_o, g_o = o.adjoint_step(f, lam_next, probes, src)

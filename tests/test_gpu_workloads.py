@@ -1,0 +1,75 @@
+"""Reduced-precision storage on the urban subdomain against the oracle (needs an MI355X).
+
+128 x 128 x 64 copy of the urban block (buildings clipped to 48 cells),
+100 steps: FP32 <= 2e-5 and shifted binary16 <= 5e-4 in max |du| over the
+fluid cells and components against the FP64 oracle; bfloat16 is reported.
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import oracle_for, oracle_init
+from paper_2607_04516_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+binding = pytest.importorskip("paper_2607_04516_amd.binding")
+
+
+@pytest.fixture(scope="module")
+def subdomain_reference():
+    w = workloads.urban_subdomain("f64", 100)
+    o = oracle_for(w)
+    f = o.run(oracle_init(o, w), 100)
+    _, u, _ = o.macros(f)
+    return w, u
+
+
+@pytest.mark.parametrize("storage,bar", [("f32", 2e-5), ("f16s", 5e-4), ("bf16s", None)])
+def test_subdomain_100_steps_velocity(subdomain_reference, storage, bar):
+    w, uo = subdomain_reference
+    print(f"case: urban subdomain 128x128x64, {storage}, 100 steps", flush=True)
+    lat = binding.from_workload(w, storage=storage)
+    lat.step(100)
+    _, u, _ = lat.macros()
+    torch.cuda.synchronize()
+    m = ~w.solid.astype(bool)
+    err = float(np.abs(u.double().cpu().numpy() - uo)[:, m].max())
+    print(f"{storage}: max |du| = {err:.3e}", flush=True)
+    if bar is not None:
+        assert err <= bar
+    else:
+        assert np.isfinite(err) and err < 5e-3
+
+
+def test_long_run_statistics_16bit_vs_fp32():
+    """512 x 512 x 128 urban block, 5000 steps, velocity mean and RMS sampled
+    every 10 steps over the second half: 16-bit storage against FP32.
+    Turbulent runs diverge point by point, so the comparison is statistical
+    (parity unpinned): relative L2 of the mean field <= 1% and of the RMS field
+    <= 5% for shifted binary16; bfloat16 is reported."""
+    w = workloads.urban_block("f32", 5000)
+    fluid = torch.from_numpy(~w.solid.astype(bool)).cuda()
+    stats = {}
+    for st in ("f32", "f16s", "bf16s"):
+        print(f"case: urban block 512x512x128, {st}, 5000 steps", flush=True)
+        lat = binding.from_workload(w, storage=st)
+        lat.step(2500)
+        acc = torch.zeros(6, w.nz, w.ny, w.nx, dtype=torch.float32, device="cuda")
+        lat.set_stats(acc, 10)
+        lat.step(2500)
+        lat.set_stats(None, 0)
+        torch.cuda.synchronize()
+        mean = acc[:3] / 250.0
+        rms = (acc[3:] / 250.0 - mean * mean).clamp_min(0).sqrt()
+        stats[st] = (mean * fluid, rms * fluid)
+        lat.close()
+    m32, r32 = stats["f32"]
+    rel = {}
+    for st in ("f16s", "bf16s"):
+        m, r = stats[st]
+        rel[st] = (float(torch.linalg.vector_norm(m - m32) / torch.linalg.vector_norm(m32)),
+                   float(torch.linalg.vector_norm(r - r32) / torch.linalg.vector_norm(r32)))
+        print(f"{st}: relative L2 of the mean {rel[st][0]:.3e}, of the RMS {rel[st][1]:.3e}", flush=True)
+    assert rel["f16s"][0] <= 0.01 and rel["f16s"][1] <= 0.05
+    assert np.isfinite(rel["bf16s"][0]) and rel["bf16s"][0] < 0.1
