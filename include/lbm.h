@@ -272,7 +272,9 @@ int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
  * or NULL.  g_inflow: device real [2][6][nz][3]; [0] += the gradient of the
  * loss with respect to each inflow face profile u_in(face, z) through the
  * step t -> t+1, as a compensated (Neumaier) sum with [1] the compensation.
- * Solid and inflow cells get lam = 0. */
+ * Solid and inflow cells get lam = 0.  The face-shell and inflow-gradient
+ * kernels run on an internal side stream forked from and joined back into
+ * the context's stream, so the call stays ordered like any other call on it. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
                      const void *probe_src, void *g_inflow);
 

@@ -298,8 +298,13 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
     if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
     const int x = cx * 64 + lane;
     const auto& O = class_offsets(otab, row_class(g, y, z));
-    const WaveMask WM = wave_mask(wave_idx, wave_tab, wave);
-    const uint64_t own = mask_word(mask, row * g.wpr + cx);
+    // masks from the cached mask rows (the adjoint arrays are 32-bit or wider)
+    RowWin W;
+    load_rows(W, mask, g, cx, y, z);
+    const uint64_t own = W.c[1][1];
+    uint64_t any = 0;
+    adj_static_for<1, NQ>([&](auto ic) { any |= solid_src_mask<decltype(ic)::value>(W); });
+    const bool solid_any = uniform_u64(any) != 0;
     if (x < B.x0 || x > B.x1) return;
     const long long cell = (long long)x + (long long)g.nx * row;
     const uint32_t off = (uint32_t)cell * (uint32_t)sizeof(R);
@@ -310,7 +315,7 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
         return;
     }
     R ls[NQ], h[NQ];
-    if (!WM.m) {
+    if (!solid_any) {
         adj_static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             ls[opp(I)] = *(const R*)(lbase + O.odd[I] + off);
@@ -321,7 +326,7 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
             if constexpr (I == 0) {
                 ls[0] = *(const R*)(lbase + off);
             } else {
-                const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], WM.template get<I>());
+                const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], solid_src_mask<I>(W));
                 ls[opp(I)] = *(const R*)(lbase + O.lo[I] + so);
             }
         });
@@ -468,28 +473,45 @@ k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_t, typename Code
 
 template <int K>
 static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
-                            int np, const void* probe_src, void* g_inflow, hipStream_t s)
+                            int np, const void* probe_src, void* g_inflow, const Streams& st)
 {
     using C = Codec<K>;
     using R = typename C::real;
     const Phys<R> P = phys_of<K>(d);
     const Geo& g = d.g;
+    const hipStream_t s = st.main;
+    // The interior kernel (bandwidth-bound) and the face-shell and inflow
+    // kernels (latency-bound, few waves) write disjoint outputs and only read
+    // lam_next and f_t, so the latter run on the side stream alongside it;
+    // the probe sources add into lam after both.
+    const bool fork = st.side != nullptr;
+    const hipStream_t s2 = fork ? st.side : s;
+    hipError_t e;
+    if (fork) {
+        if ((e = hipEventRecord(st.fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s2, st.fork, 0)) != hipSuccess) return e;
+    }
     if (g_inflow) {
         // the inflow gradient reads lam_next before lam is written (lam != lam_next)
         for (int F = 0; F < 6; F++) {
             if (g.face[F] != F_INFLOW) continue;
-            hipLaunchKernelGGL((k_adjoint_inflow<K>), dim3(g.nz), dim3(ADJ_RED), 0, s, (const R*)lam_next, d.mask,
+            hipLaunchKernelGGL((k_adjoint_inflow<K>), dim3(g.nz), dim3(ADJ_RED), 0, s2, (const R*)lam_next, d.mask,
                                d.prof, g, P, F, (R*)g_inflow);
         }
     }
+    if (d.adj_list_n > 0)
+        hipLaunchKernelGGL((k_adjoint_cells<K>), dim3((unsigned)((d.adj_list_n + 255) / 256)), dim3(256), 0, s2,
+                           (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,
+                           d.adj_list_n);
     const long long nwaves = (long long)g.ncx * g.ny * g.nz;
     hipLaunchKernelGGL((k_adjoint_main<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
                        (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, d.wave_idx, d.wave_tab, g,
                        P, d.off_adj, nwaves);
-    if (d.adj_list_n > 0)
-        hipLaunchKernelGGL((k_adjoint_cells<K>), dim3((unsigned)((d.adj_list_n + 255) / 256)), dim3(256), 0, s,
-                           (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,
-                           d.adj_list_n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (fork) {
+        if ((e = hipEventRecord(st.join, s2)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, st.join, 0)) != hipSuccess) return e;
+    }
     if (probe_src && np > 0)
         hipLaunchKernelGGL((k_adjoint_probes<K>), dim3(1), dim3(PROBE_CHUNK), 0, s, (const typename C::store*)f_t, (R*)lam,
                            d.mask, g, P, probes, np, (const R*)probe_src);
@@ -497,7 +519,7 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
 }
 
 hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
-                          int np, const void* probe_src, void* g_inflow, hipStream_t s)
+                          int np, const void* probe_src, void* g_inflow, const Streams& s)
 {
     switch (d.codec) {
         case 0: return adjoint_k<0>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);

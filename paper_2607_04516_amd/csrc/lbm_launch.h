@@ -141,7 +141,15 @@ int flux_partial_count();
 // Wave-mask table: pass 0 writes a 0/1 flag per wave into idx (solid
 // neighbour or not); pass 1 fills tab for the waves whose idx >= 0.
 hipError_t launch_wave_masks(const DevCtx& d, int* idx, uint64_t* tab, int pass, hipStream_t s);
+// The caller's stream plus an optional side stream (non-blocking, default
+// priority) and two events for a fork/join around independent kernels.
+struct Streams {
+    hipStream_t main;
+    hipStream_t side;   // nullptr: everything on main
+    hipEvent_t fork, join;
+};
+
 hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
-                          int np, const void* probe_src, void* g_inflow, hipStream_t s);
+                          int np, const void* probe_src, void* g_inflow, const Streams& s);
 
 }  // namespace lbm

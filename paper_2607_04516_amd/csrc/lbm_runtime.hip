@@ -50,6 +50,8 @@ struct lbm_ctx {
     unsigned* push_list = nullptr;
     unsigned* adj_list = nullptr;
     StepOff* offsets = nullptr;     // [27] row-class slot offsets: odd, push, adjoint
+    hipStream_t side = nullptr;     // side stream for kernels that overlap the adjoint's interior kernel
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int* wave_idx = nullptr;        // per wave: entry in wave_tab or -1
     uint64_t* wave_tab = nullptr;   // solid-source masks of waves with a solid neighbour
     void* stats = nullptr;
@@ -103,6 +105,11 @@ static long long face_cells_host(const Geo& g, int F)
 static void free_all(lbm_ctx* c)
 {
     if (!c) return;
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    c->ev_fork = c->ev_join = nullptr;
+    c->side = nullptr;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->ev_used = 0;
@@ -898,8 +905,13 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
     if (c->d.sponge_w > 0 && c->d.sponge_s > 0.0) return fail(c, LBM_ESTATE, "adjoint step with the sponge on");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
-    HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, c->probes, c->np, probe_src, g_inflow, c->stream),
-           "adjoint step");
+    if (!c->side) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "side stream events");
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "side stream events");
+    }
+    const Streams st{c->stream, c->side, c->ev_fork, c->ev_join};
+    HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, c->probes, c->np, probe_src, g_inflow, st), "adjoint step");
     return LBM_OK;
 }
 

@@ -284,8 +284,29 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     if (y < B.y0 || y > B.y1 || z < B.z0 || z > B.z1) return;
     const int x = cx * 64 + lane;
     const auto& O = class_offsets(otab, row_class(g, y, z));
-    const WaveMask WM = wave_mask(wave_idx, wave_tab, wave);
-    const uint64_t own = mask_word(mask, row * g.wpr + cx);
+    // masks as in the odd kernel: cached mask rows for 32-bit and wider
+    // storage, the per-wave table for 16-bit storage
+    constexpr bool ROWS = sizeof(T) >= 4;
+    RowWin W;
+    WaveMask WM{nullptr};
+    uint64_t own;
+    bool solid_any;
+    if constexpr (ROWS) {
+        load_rows(W, mask, g, cx, y, z);
+        own = W.c[1][1];
+        uint64_t a = 0;
+        sfor<1, NQ>([&](auto ic) { a |= solid_src_mask<decltype(ic)::value>(W); });
+        solid_any = uniform_u64(a) != 0;
+    } else {
+        WM = wave_mask(wave_idx, wave_tab, wave);
+        own = mask_word(mask, row * g.wpr + cx);
+        solid_any = WM.m != nullptr;
+    }
+    auto smask = [&](auto ic) -> uint64_t {
+        constexpr int I = decltype(ic)::value;
+        if constexpr (ROWS) return solid_src_mask<I>(W);
+        else return WM.template get<I>();
+    };
     if (x < B.x0 || x > B.x1) return;
     const uint32_t off = (uint32_t)((long long)x + (long long)g.nx * row) * (uint32_t)sizeof(T);
     const char* sbase = (const char*)src;
@@ -304,7 +325,7 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     });
     R drho, ux, uy, uz, tau;
     collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
-    if (!WM.m) {
+    if (!solid_any) {
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             st_pop((T*)(dbase + O.odd[I] + off), C::pack(h[opp(I)]));
@@ -316,7 +337,7 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
         if constexpr (I == 0) {
             st_pop((T*)(dbase + off), C::pack(h[0]));
         } else {
-            const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], WM.template get<I>());
+            const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], smask(ic));
             st_pop((T*)(dbase + O.lo[I] + so), C::pack(h[opp(I)]));
         }
     });
