@@ -231,12 +231,64 @@ __device__ inline void collision_transpose(const R* h, R* ls, const Phys<R>& P)
 #undef LBM_ADJ_PAIR
 }
 
+// Probe sources of one cell: lam += src_p . (M c_j - u)/rho for every
+// registered probe p at the cell, in probe order; M = I without rotation,
+// M c = c - Omega x c with it (the Coriolis part of F/2 in u).  The probe
+// table lists (cell, probe) entries sorted by cell; cell0 is the first cell
+// of the cell's 64-cell chunk, whose bit in pr.bits is set.
+template <typename R>
+__device__ inline void add_probe_sources(const AdjProbes& pr, long long cell, long long cell0, const R* h,
+                                         const Phys<R>& P, R* ls)
+{
+    const R* src = (const R*)pr.src;
+    int lo = 0, hi = pr.n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)pr.cell[mid] < cell0) lo = mid + 1;
+        else hi = mid;
+    }
+    bool have = false;
+    R inv_rho = R(0), ux = R(0), uy = R(0), uz = R(0);
+    for (int e = lo; e < pr.n && (long long)pr.cell[e] < cell0 + 64; e++) {
+        if ((long long)pr.cell[e] != cell) continue;
+        if (!have) {
+            R drho;
+            moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
+            inv_rho = fast_rcp<R>(P.rho0 + drho);
+            have = true;
+        }
+        const int p = pr.id[e];
+        R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
+        const R su = sx * ux + sy * uy + sz * uz;
+        if (P.has_rot) {   // src . (M c) = (M^T src) . c, M^T s = s + (W2 x s)/2
+            const R* W2 = P.W2;
+            const R ax = sx + R(0.5) * (W2[1] * sz - W2[2] * sy);
+            const R ay = sy + R(0.5) * (W2[2] * sx - W2[0] * sz);
+            const R az = sz + R(0.5) * (W2[0] * sy - W2[1] * sx);
+            sx = ax;
+            sy = ay;
+            sz = az;
+        }
+        adj_static_for<0, NQ>([&](auto ic) {
+            constexpr int j = decltype(ic)::value;
+            constexpr V3 c = dirv(j);
+            ls[j] += (R(c.x) * sx + R(c.y) * sy + R(c.z) * sz - su) * inv_rho;
+        });
+    }
+}
+
+__device__ inline bool chunk_has_probe(const AdjProbes& pr, long long chunk)
+{
+    return pr.src && ((pr.bits[chunk >> 5] >> (chunk & 31)) & 1u);
+}
+
 // Adjoint of one cell on the general path (every boundary rule).
 template <int K>
 __device__ inline void adjoint_cell(const typename Codec<K>::store* __restrict__ f_t,
                                     const typename Codec<K>::real* __restrict__ lam_next,
                                     typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
-                                    const Geo& g, const Phys<typename Codec<K>::real>& P, int x, int y, int z)
+                                    const Geo& g, const Phys<typename Codec<K>::real>& P, const AdjProbes& pr, int x,
+                                    int y, int z)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -254,23 +306,11 @@ __device__ inline void adjoint_cell(const typename Codec<K>::store* __restrict__
 #pragma unroll
     for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
     collision_transpose<R>(h, ls, P);
+    const long long row = (long long)y + (long long)g.ny * z;
+    if (chunk_has_probe(pr, (x >> 6) + (long long)g.ncx * row))
+        add_probe_sources<R>(pr, n, n - (x & 63), h, P, ls);
 #pragma unroll
     for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] = ls[j];
-}
-
-// General path over a list of cells (the two-layer shell next to the faces).
-template <int K>
-__global__ void __launch_bounds__(256)
-k_adjoint_cells(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
-                typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask, Geo g,
-                Phys<typename Codec<K>::real> P, const unsigned* __restrict__ cells, long long ncells)
-{
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t >= ncells) return;
-    const long long n = cells[t];
-    const int x = (int)(n % g.nx);
-    const long long row = n / g.nx;
-    adjoint_cell<K>(f_t, lam_next, lam, mask, g, P, x, (int)(row % g.ny), (int)(row / g.ny));
 }
 
 // Cells of main_box(g, 1): the transposed streaming reduces to
@@ -279,17 +319,14 @@ k_adjoint_cells(const typename Codec<K>::store* __restrict__ f_t, const typename
 // 64-cell chunk of a row; the slot of each direction is one shared lane
 // offset plus a wave-uniform base, selected per lane by the solid lane mask.
 template <int K>
-__global__ void __launch_bounds__(256)
-k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
-               typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
-               const int* __restrict__ wave_idx, const uint64_t* __restrict__ wave_tab, Geo g,
-               Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab, long long nwaves)
+__device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__ f_t,
+                                    const typename Codec<K>::real* __restrict__ lam_next,
+                                    typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
+                                    const Geo& g, const Phys<typename Codec<K>::real>& P,
+                                    const StepOff* __restrict__ otab, const AdjProbes& pr, long long wave)
 {
     using C = Codec<K>;
     using R = typename C::real;
-    using T = typename C::store;
-    const long long wave = blockIdx.x * 4ll + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= nwaves) return;
     const int lane = threadIdx.x & 63;
     const int cx = (int)(wave % g.ncx);
     const long long row = wave / g.ncx;
@@ -309,11 +346,8 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
     const long long cell = (long long)x + (long long)g.nx * row;
     const uint32_t off = (uint32_t)cell * (uint32_t)sizeof(R);
     const char* lbase = (const char*)lam_next;
-    if ((own >> lane) & 1ull) {
-#pragma unroll
-        for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = R(0);
-        return;
-    }
+    // a solid lane stores 0 with the same store instructions as the rest
+    const bool solid_lane = (own >> lane) & 1ull;
     R ls[NQ], h[NQ];
     if (!solid_any) {
         adj_static_for<0, NQ>([&](auto ic) {
@@ -331,26 +365,31 @@ k_adjoint_main(const typename Codec<K>::store* __restrict__ f_t, const typename 
             }
         });
     }
+    if (!solid_lane) {
 #pragma unroll
-    for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + cell]);
+        for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + cell]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NQ; i++) h[i] = R(0);
+    }
     collision_transpose<R>(h, ls, P);
+    if (chunk_has_probe(pr, wave) && !solid_lane) add_probe_sources<R>(pr, cell, cell - lane, h, P, ls);
 #pragma unroll
-    for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = ls[j];
+    for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = solid_lane ? R(0) : ls[j];
 }
 
-// dL/du_in(face F, height z): one block per z, a fixed-order tree over the
-// face's inflow cells at that height, then a compensated (Neumaier) update
-// of g[0] (sum) and g[1] (compensation).
+// dL/du_in(face F, height z): one block per (F, z), a fixed-order tree over
+// the face's inflow cells at that height, then a compensated (Neumaier)
+// update of g[0] (sum) and g[1] (compensation).
 constexpr int ADJ_RED = 256;
 
 template <int K>
-__global__ void __launch_bounds__(ADJ_RED)
-k_adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next, const uint64_t* __restrict__ mask,
-                 const double* __restrict__ prof, Geo g, Phys<typename Codec<K>::real> P, int F,
-                 typename Codec<K>::real* gacc)
+__device__ inline void adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next,
+                                      const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+                                      const Geo& g, const Phys<typename Codec<K>::real>& P, int F, int zz,
+                                      typename Codec<K>::real* gacc)
 {
     using R = typename Codec<K>::real;
-    const int zz = blockIdx.x;
     const int a = F >> 1;
     // cells of face F at height zz
     long long count;
@@ -404,128 +443,71 @@ k_adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next, const uin
     }
 }
 
-// Probe sources: lam(x_p) += src_p . (M c_j - u)/rho for the registered
-// probes; M = I without rotation, M c = c - Omega x c with it (the Coriolis
-// part of F/2 in u).  One block: each thread forms the 19 contributions of
-// one probe into LDS; then the first probe of every cell adds, in probe
-// order, the contributions of all probes of that cell and updates lam once,
-// so repeated cells are handled without races and the result does not
-// depend on scheduling.  Probes are taken 256 at a time.
-constexpr int PROBE_CHUNK = 256;
-
+// One adjoint step in one launch, blocks in the order of the context's
+// block schedule: per-cell blocks take the listed face-shell cells on the
+// general path, inflow blocks the inflow gradient (one per INFLOW face and
+// height; none without g), wave blocks the waves of main_box(g, 1).  All of
+// them only read f_t and lam_next and write disjoint parts of lam and g, so
+// the latency-bound per-cell and inflow blocks run alongside the interior,
+// each next to the wave blocks of its rows.
 template <int K>
-__global__ void __launch_bounds__(PROBE_CHUNK)
-k_adjoint_probes(const typename Codec<K>::store* __restrict__ f_t, typename Codec<K>::real* lam,
-                 const uint64_t* __restrict__ mask, Geo g, Phys<typename Codec<K>::real> P, const int* probes, int np,
-                 const typename Codec<K>::real* src)
+__global__ void __launch_bounds__(256, K == 0 ? 3 : 4)
+k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
+          typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
+          const double* __restrict__ prof, Geo g, Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab,
+          long long nwaves, const unsigned* __restrict__ cells, long long ncells, const unsigned* __restrict__ sched,
+          typename Codec<K>::real* gacc, AdjProbes pr)
 {
-    using C = Codec<K>;
-    using R = typename C::real;
-    __shared__ long long cell[PROBE_CHUNK];
-    __shared__ R con[PROBE_CHUNK][NQ];
-    const int t = threadIdx.x;
-    for (int base = 0; base < np; base += PROBE_CHUNK) {
-        const int p = base + t;
-        const int cnt = min(PROBE_CHUNK, np - base);
-        long long n = -1;
-        if (p < np) {
-            const int x = probes[3 * p], y = probes[3 * p + 1], z = probes[3 * p + 2];
-            if (!solid_at(mask, g, x, y, z) && inflow_face_of(g, x, y, z) < 0) {
-                n = cidx(g, x, y, z);
-                R h[NQ];
-                for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + n]);
-                R drho, ux, uy, uz;
-                moments_pairs<R, 1>(h, P, drho, ux, uy, uz);
-                const R inv_rho = fast_rcp<R>(P.rho0 + drho);
-                R sx = src[3 * p], sy = src[3 * p + 1], sz = src[3 * p + 2];
-                const R su = sx * ux + sy * uy + sz * uz;
-                if (P.has_rot) {   // src . (M c) = (M^T src) . c, M^T s = s + (W2 x s)/2
-                    const R* W2 = P.W2;
-                    const R ax = sx + R(0.5) * (W2[1] * sz - W2[2] * sy);
-                    const R ay = sy + R(0.5) * (W2[2] * sx - W2[0] * sz);
-                    const R az = sz + R(0.5) * (W2[0] * sy - W2[1] * sx);
-                    sx = ax;
-                    sy = ay;
-                    sz = az;
-                }
-                for (int j = 0; j < NQ; j++) {
-                    const V3 c = dirv(j);
-                    con[t][j] = (R(c.x) * sx + R(c.y) * sy + R(c.z) * sz - su) * inv_rho;
-                }
-            }
-        }
-        cell[t] = n;
-        __syncthreads();
-        bool first = n >= 0;
-        for (int u = 0; u < t && first; u++) first = cell[u] != n;
-        if (first) {
-            R acc[NQ];
-            for (int j = 0; j < NQ; j++) acc[j] = con[t][j];
-            for (int u = t + 1; u < cnt; u++)
-                if (cell[u] == n)
-                    for (int j = 0; j < NQ; j++) acc[j] += con[u][j];
-            for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + n] += acc[j];
-        }
-        __threadfence();
-        __syncthreads();
+    const unsigned code = sched[blockIdx.x];
+    const unsigned b = code & 0x3fffffffu;
+    const unsigned kind = code >> 30;
+    if (kind == 0) {
+        const long long t = b * 256ll + threadIdx.x;
+        if (t >= ncells) return;
+        const long long n = cells[t];
+        const long long row = n / g.nx;
+        adjoint_cell<K>(f_t, lam_next, lam, mask, g, P, pr, (int)(n % g.nx), (int)(row % g.ny), (int)(row / g.ny));
+        return;
     }
+    if (kind == 1) {
+        if (!gacc) return;
+        const int k = (int)(b / (unsigned)g.nz);
+        const int zz = (int)(b % (unsigned)g.nz);
+        int F = 0;
+        for (int seen = 0; F < 6; F++)
+            if (g.face[F] == F_INFLOW && seen++ == k) break;
+        adjoint_inflow<K>(lam_next, mask, prof, g, P, F, zz, gacc);
+        return;
+    }
+    const long long wave = (long long)b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    adjoint_wave<K>(f_t, lam_next, lam, mask, g, P, otab, pr, wave);
 }
 
 template <int K>
-static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
-                            int np, const void* probe_src, void* g_inflow, const Streams& st)
+static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_next, void* lam,
+                            const void* probe_src, void* g_inflow, hipStream_t s)
 {
     using C = Codec<K>;
     using R = typename C::real;
-    const Phys<R> P = phys_of<K>(d);
     const Geo& g = d.g;
-    const hipStream_t s = st.main;
-    // The interior kernel (bandwidth-bound) and the face-shell and inflow
-    // kernels (latency-bound, few waves) write disjoint outputs and only read
-    // lam_next and f_t, so the latter run on the side stream alongside it;
-    // the probe sources add into lam after both.
-    const bool fork = st.side != nullptr;
-    const hipStream_t s2 = fork ? st.side : s;
-    hipError_t e;
-    if (fork) {
-        if ((e = hipEventRecord(st.fork, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(s2, st.fork, 0)) != hipSuccess) return e;
-    }
-    if (g_inflow) {
-        // the inflow gradient reads lam_next before lam is written (lam != lam_next)
-        for (int F = 0; F < 6; F++) {
-            if (g.face[F] != F_INFLOW) continue;
-            hipLaunchKernelGGL((k_adjoint_inflow<K>), dim3(g.nz), dim3(ADJ_RED), 0, s2, (const R*)lam_next, d.mask,
-                               d.prof, g, P, F, (R*)g_inflow);
-        }
-    }
-    if (d.adj_list_n > 0)
-        hipLaunchKernelGGL((k_adjoint_cells<K>), dim3((unsigned)((d.adj_list_n + 255) / 256)), dim3(256), 0, s2,
-                           (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, g, P, d.adj_list,
-                           d.adj_list_n);
     const long long nwaves = (long long)g.ncx * g.ny * g.nz;
-    hipLaunchKernelGGL((k_adjoint_main<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
-                       (const typename C::store*)f_t, (const R*)lam_next, (R*)lam, d.mask, d.wave_idx, d.wave_tab, g,
-                       P, d.off_adj, nwaves);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (fork) {
-        if ((e = hipEventRecord(st.join, s2)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(s, st.join, 0)) != hipSuccess) return e;
-    }
-    if (probe_src && np > 0)
-        hipLaunchKernelGGL((k_adjoint_probes<K>), dim3(1), dim3(PROBE_CHUNK), 0, s, (const typename C::store*)f_t, (R*)lam,
-                           d.mask, g, P, probes, np, (const R*)probe_src);
+    AdjProbes pr = d.probes;
+    pr.src = pr.n > 0 ? probe_src : nullptr;
+    hipLaunchKernelGGL((k_adjoint<K>), dim3(d.adj_sched_n), dim3(256), 0, s, (const typename C::store*)f_t,
+                       (const R*)lam_next, (R*)lam, d.mask, d.prof, g, phys_of<K>(d), d.off_adj, nwaves, d.adj_list,
+                       d.adj_list_n, d.adj_sched, (R*)g_inflow, pr);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
-                          int np, const void* probe_src, void* g_inflow, const Streams& s)
+hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const void* probe_src,
+                          void* g_inflow, hipStream_t s)
 {
     switch (d.codec) {
-        case 0: return adjoint_k<0>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
-        case 1: return adjoint_k<1>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
-        case 2: return adjoint_k<2>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
-        case 3: return adjoint_k<3>(d, f_t, lam_next, lam, probes, np, probe_src, g_inflow, s);
+        case 0: return adjoint_k<0>(d, f_t, lam_next, lam, probe_src, g_inflow, s);
+        case 1: return adjoint_k<1>(d, f_t, lam_next, lam, probe_src, g_inflow, s);
+        case 2: return adjoint_k<2>(d, f_t, lam_next, lam, probe_src, g_inflow, s);
+        case 3: return adjoint_k<3>(d, f_t, lam_next, lam, probe_src, g_inflow, s);
         default: return hipErrorInvalidValue;
     }
 }

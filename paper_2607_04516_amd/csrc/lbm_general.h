@@ -1,0 +1,121 @@
+// The general per-cell path of the collide-and-stream step: every boundary
+// rule, one cell per lane.  Shared by the step kernels (lbm_kernels.hip) and
+// the push kernel, which runs it for its face layer in the same launch.
+#pragma once
+
+#include "lbm_device.h"
+
+#include <type_traits>
+
+namespace lbm {
+
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn)
+{
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(fn);
+    }
+}
+
+constexpr int MODE_EVEN = 0, MODE_ODD = 1, MODE_PUSH = 2;
+
+// Every boundary rule, per cell: the step of one cell (x, y, z) in any mode.
+template <int K, int MODE, bool STATS>
+__device__ inline void general_cell(typename Codec<K>::store* dst, const typename Codec<K>::store* src,
+                                    const uint64_t* __restrict__ mask, const double* __restrict__ uin,
+                                    const typename Codec<K>::store* __restrict__ ghost, const Geo& g, const Lay& ls,
+                                    const Lay& ld, const Phys<typename Codec<K>::real>& P,
+                                    typename Codec<K>::real* stats, int x, int y, int z)
+{
+    using C = Codec<K>;
+    using R = typename C::real;
+    const long long ns = cell_index(ls, g.ny, x, y, z);
+    const long long nd = cell_index(ld, g.ny, x, y, z);
+    if (solid_at(mask, g, x, y, z)) {
+        if constexpr (MODE == MODE_PUSH) {
+            static_for<0, NQ>([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                dst[(long long)I * ld.S + nd] = C::enc(R(0));
+            });
+        }
+        return;
+    }
+    R h[NQ];
+    R ux, uy, uz;
+    const int inf = inflow_face_of(g, x, y, z);
+    if (inf >= 0) {
+        // inflow cell: post-collision state is feq(rho0, u_in(z)) whatever it held
+        load_inflow<R>(uin, g, inf, x, y, z, ux, uy, uz);
+        equilibrium_shifted<R>(P.rho0, R(0), ux, uy, uz, h);
+#pragma unroll
+        for (int i = 0; i < NQ; i++) h[i] *= R(C::SC);
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (MODE == MODE_EVEN) {
+                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
+            } else if constexpr (MODE == MODE_PUSH) {
+                // canonical output of an inflow cell is its own equilibrium
+                dst[(long long)I * ld.S + nd] = C::pack(h[I]);
+                const Res r = resolve_plain<I>(g, mask, x, y, z);
+                if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
+                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+            } else {
+                const Res r = resolve_plain<I>(g, mask, x, y, z);
+                if (r.kind == 0)
+                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+            }
+        });
+    } else {
+        // gather
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (MODE == MODE_ODD) {
+                int qx, qy, qz, owner;
+                if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
+                    h[I] = C::raw(ghost[ghost_index<I>(g, owner, x, y, z)]);
+                } else {
+                    const Res r = resolve_plain<I>(g, mask, x, y, z);
+                    h[I] = C::raw(src[(long long)r.dir * ls.S + cell_index(ls, g.ny, r.x, r.y, r.z)]);
+                }
+            } else {
+                h[I] = C::raw(src[(long long)I * ls.S + ns]);
+            }
+        });
+        R drho, tau;
+        collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
+        // scatter
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (MODE == MODE_EVEN) {
+                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
+            } else {
+                int qx, qy, qz, owner;
+                if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
+                    // opp(I) leaves through the outflow face: kept only as the
+                    // bounce-back of a solid inner neighbour
+                    if (solid_at(mask, g, qx, qy, qz)) dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
+                } else {
+                    const Res r = resolve_plain<I>(g, mask, x, y, z);
+                    if (r.kind == 0) {
+                        if constexpr (MODE == MODE_PUSH) {
+                            if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
+                        }
+                        dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                    }
+                }
+            }
+        });
+    }
+    if constexpr (STATS) {
+        const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+        stats[n] += ux;
+        stats[g.N + n] += uy;
+        stats[2 * g.N + n] += uz;
+        stats[3 * g.N + n] += ux * ux;
+        stats[4 * g.N + n] += uy * uy;
+        stats[5 * g.N + n] += uz * uz;
+    }
+}
+
+}  // namespace lbm

@@ -15,22 +15,12 @@
 // update needs one array and no synchronisation.  The boundary rules enter
 // only through the slot each direction resolves to (lbm_device.h).
 #include "lbm_device.h"
+#include "lbm_general.h"
 #include "lbm_launch.h"
 
 #include <type_traits>
 
 namespace lbm {
-
-template <int I, int N, class Fn>
-__device__ __forceinline__ void static_for(Fn&& fn)
-{
-    if constexpr (I < N) {
-        fn(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(fn);
-    }
-}
-
-constexpr int MODE_EVEN = 0, MODE_ODD = 1, MODE_PUSH = 2;
 
 // Wave -> (chunk, y, z) with a block order that keeps consecutive chunks of a
 // row on one XCD (blocks are dealt to the 8 XCDs round robin).
@@ -39,104 +29,6 @@ __device__ inline long long xcd_block(long long nblocks_padded)
     const long long b = blockIdx.x;
     const long long per = nblocks_padded >> 3;
     return (b & 7) * per + (b >> 3);
-}
-
-// Every boundary rule, per cell: the step of one cell (x, y, z) in any mode.
-template <int K, int MODE, bool STATS>
-__device__ inline void general_cell(typename Codec<K>::store* dst, const typename Codec<K>::store* src,
-                                    const uint64_t* __restrict__ mask, const double* __restrict__ uin,
-                                    const typename Codec<K>::store* __restrict__ ghost, const Geo& g, const Lay& ls,
-                                    const Lay& ld, const Phys<typename Codec<K>::real>& P,
-                                    typename Codec<K>::real* stats, int x, int y, int z)
-{
-    using C = Codec<K>;
-    using R = typename C::real;
-    const long long ns = cell_index(ls, g.ny, x, y, z);
-    const long long nd = cell_index(ld, g.ny, x, y, z);
-    if (solid_at(mask, g, x, y, z)) {
-        if constexpr (MODE == MODE_PUSH) {
-            static_for<0, NQ>([&](auto ic) {
-                constexpr int I = decltype(ic)::value;
-                dst[(long long)I * ld.S + nd] = C::enc(R(0));
-            });
-        }
-        return;
-    }
-    R h[NQ];
-    R ux, uy, uz;
-    const int inf = inflow_face_of(g, x, y, z);
-    if (inf >= 0) {
-        // inflow cell: post-collision state is feq(rho0, u_in(z)) whatever it held
-        load_inflow<R>(uin, g, inf, x, y, z, ux, uy, uz);
-        equilibrium_shifted<R>(P.rho0, R(0), ux, uy, uz, h);
-#pragma unroll
-        for (int i = 0; i < NQ; i++) h[i] *= R(C::SC);
-        static_for<0, NQ>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            if constexpr (MODE == MODE_EVEN) {
-                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
-            } else if constexpr (MODE == MODE_PUSH) {
-                // canonical output of an inflow cell is its own equilibrium
-                dst[(long long)I * ld.S + nd] = C::pack(h[I]);
-                const Res r = resolve_plain<I>(g, mask, x, y, z);
-                if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
-                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
-            } else {
-                const Res r = resolve_plain<I>(g, mask, x, y, z);
-                if (r.kind == 0)
-                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
-            }
-        });
-    } else {
-        // gather
-        static_for<0, NQ>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            if constexpr (MODE == MODE_ODD) {
-                int qx, qy, qz, owner;
-                if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
-                    h[I] = C::raw(ghost[ghost_index<I>(g, owner, x, y, z)]);
-                } else {
-                    const Res r = resolve_plain<I>(g, mask, x, y, z);
-                    h[I] = C::raw(src[(long long)r.dir * ls.S + cell_index(ls, g.ny, r.x, r.y, r.z)]);
-                }
-            } else {
-                h[I] = C::raw(src[(long long)I * ls.S + ns]);
-            }
-        });
-        R drho, tau;
-        collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
-        // scatter
-        static_for<0, NQ>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            if constexpr (MODE == MODE_EVEN) {
-                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
-            } else {
-                int qx, qy, qz, owner;
-                if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
-                    // opp(I) leaves through the outflow face: kept only as the
-                    // bounce-back of a solid inner neighbour
-                    if (solid_at(mask, g, qx, qy, qz)) dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
-                } else {
-                    const Res r = resolve_plain<I>(g, mask, x, y, z);
-                    if (r.kind == 0) {
-                        if constexpr (MODE == MODE_PUSH) {
-                            if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
-                        }
-                        dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
-                    }
-                }
-            }
-        });
-    }
-    if constexpr (STATS) {
-        const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
-        stats[n] += ux;
-        stats[g.N + n] += uy;
-        stats[2 * g.N + n] += uz;
-        stats[3 * g.N + n] += ux * ux;
-        stats[4 * g.N + n] += uy * uy;
-        stats[5 * g.N + n] += uz * uz;
-    }
 }
 
 // --------------------------------------------------------------------------
@@ -220,22 +112,6 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
     // ---------------- general path: every boundary rule, per lane ----------------
     if (x >= g.nx) return;
     general_cell<K, MODE, STATS>(dst, src, mask, uin, ghost, g, ls, ld, P, stats, x, y, z);
-}
-
-// One cell on the general path, for a list of cells (thread per cell).
-template <int K, int MODE>
-__global__ void __launch_bounds__(256)
-k_cells(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const uint64_t* __restrict__ mask,
-        const double* __restrict__ uin, const typename Codec<K>::store* __restrict__ ghost, Geo g, Lay ls, Lay ld,
-        Phys<typename Codec<K>::real> P, const unsigned* __restrict__ cells, long long ncells)
-{
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t >= ncells) return;
-    const long long n = cells[t];
-    const int x = (int)(n % g.nx);
-    const long long row = n / g.nx;
-    general_cell<K, MODE, false>(dst, src, mask, uin, ghost, g, ls, ld, P, (typename Codec<K>::real*)nullptr, x,
-                                 (int)(row % g.ny), (int)(row / g.ny));
 }
 
 // --------------------------------------------------------------------------
@@ -717,19 +593,6 @@ hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s)
     LBM_DISPATCH(d.codec, {
         if (stats) return general_odd_k<K, true>(d, stats, s);
         return general_odd_k<K, false>(d, stats, s);
-    });
-}
-
-// General-path push for the listed cells (the face layer), canonical layout.
-hipError_t launch_push_cells(const DevCtx& d, const void* src, void* dst, hipStream_t s)
-{
-    if (d.push_list_n == 0) return hipSuccess;
-    LBM_DISPATCH(d.codec, {
-        hipLaunchKernelGGL((k_cells<K, MODE_PUSH>), dim3(blocks_for(d.push_list_n, 256)), dim3(256), 0, s,
-                           (typename Codec<K>::store*)dst, (const typename Codec<K>::store*)src, d.mask, d.uin,
-                           (const typename Codec<K>::store*)d.ghost, d.g, canonical(d), canonical(d), phys_of<K>(d),
-                           d.push_list, d.push_list_n);
-        return hipGetLastError();
     });
 }
 

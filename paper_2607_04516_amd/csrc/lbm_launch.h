@@ -10,6 +10,17 @@ namespace lbm {
 
 struct StepOff;
 
+// Probe table of the adjoint step: (cell, probe) entries sorted by canonical
+// cell index (probe order within a cell) and one bit per 64-cell chunk of a
+// row (chunk cx + ncx * row) that holds a probe cell.
+struct AdjProbes {
+    const uint32_t* bits;
+    const unsigned* cell;
+    const int* id;
+    int n;              // entries; 0: no probes
+    const void* src;    // per call: [np][3] dL/du at the probes, or nullptr
+};
+
 // Everything a kernel launch needs to know about one context.
 struct DevCtx {
     Geo g;
@@ -25,6 +36,10 @@ struct DevCtx {
     long long push_list_n;
     const unsigned* adj_list;  // canonical indices of the two-layer face shell (general-path adjoint)
     long long adj_list_n;
+    const unsigned* push_sched;  // block order of the push launch (kind << 30 | index)
+    unsigned push_sched_n;
+    const unsigned* adj_sched;   // block order of the adjoint launch
+    unsigned adj_sched_n;
     const int* wave_idx;       // per wave (chunk, row): entry in wave_tab, -1 without solid neighbour
     const uint64_t* wave_tab;  // [entries][18] solid-source masks
     const StepOff* off_odd;    // [9] row-class offsets, padded layout, store elements
@@ -34,6 +49,7 @@ struct DevCtx {
     double omega[3];      // rotation vector in lattice units (Coriolis); zero: none
     int sponge_w;         // sponge / buffer layer width; 0: off
     double sponge_s;      // its strength s_max
+    AdjProbes probes;     // registered probes (src unset)
 };
 
 // Collision parameters of a context in the codec's arithmetic type.
@@ -122,7 +138,6 @@ hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s);
 hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s);
 hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s);
 hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s);
-hipError_t launch_push_cells(const DevCtx& d, const void* src, void* dst, hipStream_t s);
 hipError_t launch_outflow_ghost(const DevCtx& d, hipStream_t s);
 hipError_t launch_outflow_copy(const DevCtx& d, void* arr, int canonical_layout, hipStream_t s);
 hipError_t launch_init(const DevCtx& d, const double* u0_dev, double amp, uint64_t seed, hipStream_t s);
@@ -141,15 +156,7 @@ int flux_partial_count();
 // Wave-mask table: pass 0 writes a 0/1 flag per wave into idx (solid
 // neighbour or not); pass 1 fills tab for the waves whose idx >= 0.
 hipError_t launch_wave_masks(const DevCtx& d, int* idx, uint64_t* tab, int pass, hipStream_t s);
-// The caller's stream plus an optional side stream (non-blocking, default
-// priority) and two events for a fork/join around independent kernels.
-struct Streams {
-    hipStream_t main;
-    hipStream_t side;   // nullptr: everything on main
-    hipEvent_t fork, join;
-};
-
-hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const int* probes,
-                          int np, const void* probe_src, void* g_inflow, const Streams& s);
+hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const void* probe_src,
+                          void* g_inflow, hipStream_t s);
 
 }  // namespace lbm

@@ -44,14 +44,15 @@ struct lbm_ctx {
     double* u0 = nullptr;   // device [nz][3] scratch for initialisation
     int* probes = nullptr;  // device [np][3]
     int np = 0;
+    void* probe_tab = nullptr;  // device: adjoint probe table (chunk bits, sorted cells, probe ids)
     double* red_partial = nullptr;
     double* red_out = nullptr;  // device [5]
     unsigned* odd_list = nullptr;
     unsigned* push_list = nullptr;
     unsigned* adj_list = nullptr;
+    unsigned* push_sched = nullptr;  // block order of the push launch
+    unsigned* adj_sched = nullptr;   // block order of the adjoint launch
     StepOff* offsets = nullptr;     // [27] row-class slot offsets: odd, push, adjoint
-    hipStream_t side = nullptr;     // side stream for kernels that overlap the adjoint's interior kernel
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int* wave_idx = nullptr;        // per wave: entry in wave_tab or -1
     uint64_t* wave_tab = nullptr;   // solid-source masks of waves with a solid neighbour
     void* stats = nullptr;
@@ -102,21 +103,55 @@ static long long face_cells_host(const Geo& g, int F)
     return a == 0 ? (long long)g.ny * g.nz : (a == 1 ? (long long)g.nx * g.nz : (long long)g.nx * g.ny);
 }
 
+// Block order of a launch that mixes per-cell blocks (cells of a list, 256
+// per block) and inflow-gradient blocks (one per INFLOW face and height)
+// with wave blocks (4 chunks of 64 cells each): every block is placed at the
+// first row it touches, the per-cell and inflow blocks ahead of the wave
+// blocks of that row.  Blocks are dispatched in order, so the scattered
+// loads of a per-cell block find the lines the wave blocks of its rows
+// fetch at about the same time.  Entry: kind << 30 | index, kind 0 per-cell,
+// 1 inflow, 2 wave block.
+static std::vector<unsigned> block_schedule(const Geo& g, const std::vector<unsigned>& cells, bool inflow)
+{
+    struct B {
+        long long row;
+        unsigned code;
+    };
+    std::vector<B> b;
+    const long long nwaves = (long long)g.ncx * g.ny * g.nz;
+    for (size_t s = 0; s * 256 < cells.size(); s++) b.push_back({(long long)(cells[s * 256] / (unsigned)g.nx), (unsigned)s});
+    if (inflow) {
+        int k = 0;
+        for (int F = 0; F < 6; F++) {
+            if (g.face[F] != F_INFLOW) continue;
+            for (int z = 0; z < g.nz; z++) {
+                const int zr = (F >> 1) == 2 ? ((F & 1) ? g.nz - 1 : 0) : z;
+                const long long row = (F >> 1) == 1 ? ((F & 1) ? g.ny - 1 : 0) + (long long)g.ny * zr : (long long)g.ny * zr;
+                b.push_back({row, (1u << 30) | (unsigned)(k * g.nz + z)});
+            }
+            k++;
+        }
+    }
+    for (long long m = 0; 4 * m < nwaves; m++) b.push_back({(4 * m) / g.ncx, (2u << 30) | (unsigned)m});
+    std::stable_sort(b.begin(), b.end(), [](const B& p, const B& q) {
+        return p.row != q.row ? p.row < q.row : (p.code >> 30) < (q.code >> 30);
+    });
+    std::vector<unsigned> out(b.size());
+    for (size_t i = 0; i < b.size(); i++) out[i] = b[i].code;
+    return out;
+}
+
 static void free_all(lbm_ctx* c)
 {
     if (!c) return;
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-    if (c->side) (void)hipStreamDestroy(c->side);
-    c->ev_fork = c->ev_join = nullptr;
-    c->side = nullptr;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->ev_used = 0;
     vk_destroy(c->vk);
     c->vk = nullptr;
     void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
-                    c->push_list, c->adj_list, c->uin, c->flux_cells, c->flux_red, c->wave_idx, c->wave_tab, c->offsets};
+                    c->push_list, c->adj_list, c->push_sched, c->adj_sched, c->uin, c->flux_cells, c->flux_red, c->wave_idx, c->wave_tab, c->offsets,
+                    c->probe_tab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     c->f = nullptr;
@@ -125,11 +160,15 @@ static void free_all(lbm_ctx* c)
     c->prof = nullptr;
     c->u0 = nullptr;
     c->probes = nullptr;
+    c->probe_tab = nullptr;
+    c->d.probes = AdjProbes{nullptr, nullptr, nullptr, 0, nullptr};
     c->red_partial = nullptr;
     c->red_out = nullptr;
     c->odd_list = nullptr;
     c->push_list = nullptr;
     c->adj_list = nullptr;
+    c->push_sched = nullptr;
+    c->adj_sched = nullptr;
     c->uin = nullptr;
     c->flux_cells = nullptr;
     c->flux_red = nullptr;
@@ -358,6 +397,27 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->d.push_list_n = (long long)plist.size();
     c->d.adj_list = c->adj_list;
     c->d.adj_list_n = (long long)alist.size();
+    {
+        const std::vector<unsigned> sp = block_schedule(g, plist, false), sa = block_schedule(g, alist, true);
+        if ((rc = device_alloc(c, (void**)&c->push_sched, sp.size() * sizeof(unsigned), "block order")) != LBM_OK ||
+            (rc = device_alloc(c, (void**)&c->adj_sched, sa.size() * sizeof(unsigned), "block order")) != LBM_OK) {
+            g_create_error = c->err;
+            free_all(c);
+            delete c;
+            return rc;
+        }
+        if (hipMemcpy(c->push_sched, sp.data(), sp.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->adj_sched, sa.data(), sa.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) {
+            g_create_error = "upload block order";
+            free_all(c);
+            delete c;
+            return LBM_EHIP;
+        }
+        c->d.push_sched = c->push_sched;
+        c->d.push_sched_n = (unsigned)sp.size();
+        c->d.adj_sched = c->adj_sched;
+        c->d.adj_sched_n = (unsigned)sa.size();
+    }
     c->prof_host.assign(18 * (size_t)g.nz, 0.0);
     hipError_t e = hipMemcpy(c->mask, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->prof, 0, 18 * (size_t)g.nz * sizeof(double));
@@ -842,16 +902,47 @@ int lbm_set_probes(lbm_ctx* c, const int32_t* cells, int32_t np)
         if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz)
             return fail(c, LBM_EINVAL, "probe cell outside the grid");
     }
-    if (c->probes) {
+    if (c->probes || c->probe_tab) {
         HIPCHK(c, hipStreamSynchronize(c->stream), "probe sync");
-        (void)hipFree(c->probes);
+        if (c->probes) (void)hipFree(c->probes);
+        if (c->probe_tab) (void)hipFree(c->probe_tab);
         c->probes = nullptr;
+        c->probe_tab = nullptr;
     }
     c->np = 0;
+    c->d.probes = AdjProbes{nullptr, nullptr, nullptr, 0, nullptr};
     if (np == 0) return LBM_OK;
     int rc = device_alloc(c, (void**)&c->probes, (size_t)np * 3 * sizeof(int), "probes");
     if (rc != LBM_OK) return rc;
     HIPCHK(c, hipMemcpy(c->probes, cells, (size_t)np * 3 * sizeof(int), hipMemcpyHostToDevice), "probe upload");
+    // adjoint probe table: one bit per 64-cell chunk of a row, then the
+    // (cell, probe) entries sorted by cell and, within a cell, by probe
+    const long long nchunks = (long long)g.ncx * g.ny * g.nz;
+    const size_t nwords = (size_t)((nchunks + 31) / 32);
+    std::vector<std::pair<unsigned, int>> ent((size_t)np);
+    for (int p = 0; p < np; p++)
+        ent[(size_t)p] = {(unsigned)(cells[3 * p] + (long long)g.nx * (cells[3 * p + 1] + (long long)g.ny * cells[3 * p + 2])), p};
+    std::sort(ent.begin(), ent.end());
+    std::vector<uint32_t> bits(nwords, 0u);
+    std::vector<unsigned> pc((size_t)np);
+    std::vector<int> pid((size_t)np);
+    for (size_t e = 0; e < ent.size(); e++) {
+        pc[e] = ent[e].first;
+        pid[e] = ent[e].second;
+        const long long row = (long long)ent[e].first / g.nx;
+        const long long chunk = (long long)(ent[e].first % g.nx) / 64 + (long long)g.ncx * row;
+        bits[(size_t)(chunk >> 5)] |= 1u << (chunk & 31);
+    }
+    const size_t bytes = nwords * 4 + (size_t)np * 8;
+    rc = device_alloc(c, &c->probe_tab, bytes, "probe table");
+    if (rc != LBM_OK) return rc;
+    auto* tb = (char*)c->probe_tab;
+    HIPCHK(c, hipMemcpy(tb, bits.data(), nwords * 4, hipMemcpyHostToDevice), "probe table upload");
+    HIPCHK(c, hipMemcpy(tb + nwords * 4, pc.data(), (size_t)np * 4, hipMemcpyHostToDevice), "probe table upload");
+    HIPCHK(c, hipMemcpy(tb + nwords * 4 + (size_t)np * 4, pid.data(), (size_t)np * 4, hipMemcpyHostToDevice),
+           "probe table upload");
+    c->d.probes = AdjProbes{(const uint32_t*)tb, (const unsigned*)(tb + nwords * 4),
+                            (const int*)(tb + nwords * 4 + (size_t)np * 4), np, nullptr};
     c->np = np;
     return LBM_OK;
 }
@@ -905,13 +996,7 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
     if (c->d.sponge_w > 0 && c->d.sponge_s > 0.0) return fail(c, LBM_ESTATE, "adjoint step with the sponge on");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
-    if (!c->side) {
-        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
-        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "side stream events");
-        HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "side stream events");
-    }
-    const Streams st{c->stream, c->side, c->ev_fork, c->ev_join};
-    HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, c->probes, c->np, probe_src, g_inflow, st), "adjoint step");
+    HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, probe_src, g_inflow, c->stream), "adjoint step");
     return LBM_OK;
 }
 

@@ -19,6 +19,7 @@
 //     feq(rho0, u_in), the outflow cell of an x+ OUTFLOW face reads its five
 //     entering populations from the ghost plane.
 #include "lbm_device.h"
+#include "lbm_general.h"
 #include "lbm_launch.h"
 
 #include <type_traits>
@@ -259,22 +260,73 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
 }
 
 // ---------------------------------------------------------------- push step
-// Out-of-place step on canonical (unpadded) arrays, src -> dst, for the
-// cells of main_box(g, 0): local read, collision, push of f*_opp(I) into
-// the slot the pull of I resolves to (own slot at solid neighbours and
-// across WALL faces).  The other face layers run the general per-cell code
-// afterwards (launch_push_cells), which overwrites what this kernel pushed
-// into inflow cells with their canonical equilibrium.  Solid cells get 0.
+// Out-of-place step on canonical (unpadded) arrays, src -> dst, in one
+// launch with two kinds of blocks, in the order of the context's block
+// schedule.  Per-cell blocks run the general per-cell code for the face
+// layer outside main_box(g, 0) (the listed cells); inflow cells among them
+// write their canonical equilibrium into their own slots.  Wave blocks take
+// the waves of main_box(g, 0):
+// local read, collision, push of f*_opp(I) into the slot the pull of I
+// resolves to (own slot at solid neighbours and across WALL faces).  Waves
+// next to an INFLOW face skip the pushes that land in an inflow cell, so
+// the two kinds of blocks write disjoint slots and run side by side, each
+// per-cell block next to the wave blocks of its rows.  Solid cells get 0.
+
+// Whether the push of f*_opp(I) from (x, y, z) lands in an inflow cell: the
+// pull source x - c_I resolved through FREESLIP (mirror) and PERIODIC
+// (wrap) faces lies on an INFLOW face layer.  Across a WALL face the value
+// stays in the cell's own slot; a solid source does too, which the caller
+// tests with the lane masks.  Cells of main_box(g, 0) never cross an
+// INFLOW or OUTFLOW face.
+// One axis of the resolution: the coordinate p = own - c of the pull
+// source, mirrored or wrapped; false when the value stays in the own slot.
+__device__ inline bool resolve_axis(int& p, int own, int n, int kind_lo, int kind_hi)
+{
+    if (p >= 0 && p < n) return true;
+    const int kind = p < 0 ? kind_lo : kind_hi;
+    if (kind == F_FREESLIP) p = own;
+    else if (kind == F_PERIODIC) p = p < 0 ? n - 1 : 0;
+    else return false;
+    return true;
+}
+
+template <int I>
+__device__ inline bool push_lands_in_inflow(const Geo& g, int x, int y, int z)
+{
+    constexpr V3 c = dirv(I);
+    int px = x - c.x, py = y - c.y, pz = z - c.z;
+    if constexpr (c.x != 0)
+        if (!resolve_axis(px, x, g.nx, g.face[0], g.face[1])) return false;
+    if constexpr (c.y != 0)
+        if (!resolve_axis(py, y, g.ny, g.face[2], g.face[3])) return false;
+    if constexpr (c.z != 0)
+        if (!resolve_axis(pz, z, g.nz, g.face[4], g.face[5])) return false;
+    return inflow_face_of(g, px, py, pz) >= 0;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256)
 k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::store* __restrict__ dst,
        const uint64_t* __restrict__ mask, const int* __restrict__ wave_idx, const uint64_t* __restrict__ wave_tab,
-       Geo g, Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab, long long nwaves)
+       const double* __restrict__ uin, Geo g, Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab,
+       long long nwaves, const unsigned* __restrict__ cells, long long ncells, const unsigned* __restrict__ sched)
 {
     using C = Codec<K>;
     using R = typename C::real;
     using T = typename C::store;
-    const long long wave = blockIdx.x * 4ll + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned code = sched[blockIdx.x];
+    const unsigned idx = code & 0x3fffffffu;
+    if ((code >> 30) == 0) {
+        const long long t = idx * 256ll + threadIdx.x;
+        if (t >= ncells) return;
+        const long long n = cells[t];
+        const long long r = n / g.nx;
+        const Lay L{g.N, g.nx};
+        general_cell<K, MODE_PUSH, false>(dst, src, mask, uin, nullptr, g, L, L, P, nullptr, (int)(n % g.nx),
+                                          (int)(r % g.ny), (int)(r / g.ny));
+        return;
+    }
+    const long long wave = idx * 4ll + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
     const int lane = threadIdx.x & 63;
     const int cx = (int)(wave % g.ncx);
@@ -311,21 +363,47 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     const uint32_t off = (uint32_t)((long long)x + (long long)g.nx * row) * (uint32_t)sizeof(T);
     const char* sbase = (const char*)src;
     char* dbase = (char*)dst;
-    if ((own >> lane) & 1ull) {
+    // A solid lane writes 0 into its own 19 slots with the same store
+    // instructions as the fluid lanes (no fluid lane pushes into a solid
+    // cell, so the addresses never collide).
+    const bool solid_lane = (own >> lane) & 1ull;
+    R h[NQ];
+    if (!solid_lane) {
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            st_pop((T*)(dbase + O.even[I] + off), C::pack(R(0)));
+            h[I] = C::raw(ld_pop((const T*)(sbase + O.even[I] + off)));
+        });
+    } else {
+        sfor<0, NQ>([&](auto ic) { h[decltype(ic)::value] = R(0); });
+    }
+    R drho, ux, uy, uz, tau;
+    collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
+    // INFLOW face layers next to this wave (wave-uniform): the x- layer
+    // when the chunk holds x = 1, the x+ layer when it holds x = nx - 2, the
+    // y and z layers when the row is next to them.  Only a direction whose
+    // pull source moves toward such a layer can land in an inflow cell.
+    const int x0 = cx * 64;
+    const bool in_x0 = g.face[0] == F_INFLOW && x0 <= 1, in_x1 = g.face[1] == F_INFLOW && x0 + 63 >= g.nx - 2;
+    const bool in_y0 = g.face[2] == F_INFLOW && y == 1, in_y1 = g.face[3] == F_INFLOW && y == g.ny - 2;
+    const bool in_z0 = g.face[4] == F_INFLOW && z == 1, in_z1 = g.face[5] == F_INFLOW && z == g.nz - 2;
+    if (in_x0 || in_x1 || in_y0 || in_y1 || in_z0 || in_z1) {
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            if constexpr (I == 0) {
+                st_pop((T*)(dbase + off), C::pack(solid_lane ? R(0) : h[0]));
+            } else {
+                const bool sol = solid_lane || (solid_any && ((smask(ic) >> lane) & 1ull));
+                const bool toward = (c.x == 1 && in_x0) || (c.x == -1 && in_x1) || (c.y == 1 && in_y0) ||
+                                    (c.y == -1 && in_y1) || (c.z == 1 && in_z0) || (c.z == -1 && in_z1);
+                if (toward && !sol && push_lands_in_inflow<I>(g, x, y, z)) return;
+                const uint32_t so = sol ? off + O.oo[I] : off + O.on[I];
+                st_pop((T*)(dbase + O.lo[I] + so), C::pack(solid_lane ? R(0) : h[opp(I)]));
+            }
         });
         return;
     }
-    R h[NQ];
-    sfor<0, NQ>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        h[I] = C::raw(ld_pop((const T*)(sbase + O.even[I] + off)));
-    });
-    R drho, ux, uy, uz, tau;
-    collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
-    if (!solid_any) {
+    if (!solid_any) {   // then no lane is solid either
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             st_pop((T*)(dbase + O.odd[I] + off), C::pack(h[opp(I)]));
@@ -335,10 +413,10 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         if constexpr (I == 0) {
-            st_pop((T*)(dbase + off), C::pack(h[0]));
+            st_pop((T*)(dbase + off), C::pack(solid_lane ? R(0) : h[0]));
         } else {
-            const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], smask(ic));
-            st_pop((T*)(dbase + O.lo[I] + so), C::pack(h[opp(I)]));
+            const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], smask(ic) | own);
+            st_pop((T*)(dbase + O.lo[I] + so), C::pack(solid_lane ? R(0) : h[opp(I)]));
         }
     });
 }
@@ -381,12 +459,11 @@ static hipError_t launch_push_k(const DevCtx& d, const void* src, void* dst, hip
 {
     using C = Codec<K>;
     const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
-    hipLaunchKernelGGL((k_push<K>), dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s,
-                       (const typename C::store*)src, (typename C::store*)dst, d.mask, d.wave_idx, d.wave_tab, d.g,
-                       phys_of<K>(d), d.off_push, nwaves);
+    hipLaunchKernelGGL((k_push<K>), dim3(d.push_sched_n), dim3(256), 0, s, (const typename C::store*)src,
+                       (typename C::store*)dst, d.mask, d.wave_idx, d.wave_tab, d.uin, d.g, phys_of<K>(d), d.off_push,
+                       nwaves, d.push_list, d.push_list_n, d.push_sched);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_push_cells(d, src, dst, s)) != hipSuccess) return e;
     return launch_outflow_copy(d, dst, 1, s);
 }
 
