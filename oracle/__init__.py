@@ -43,10 +43,30 @@ class _Cfg(ctypes.Structure):
                 ("delta", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("omega", ctypes.c_double * 3),
                 ("inflow_field", ctypes.c_void_p), ("sponge_strength", ctypes.c_double),
-                ("sponge_width", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("sponge_width", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("face_base", ctypes.c_void_p * 6)]
 
 
 _lib = None
+
+
+def face_shape(face, nx, ny, nz):
+    """(n2, n1) of a face's per-cell arrays: cell (j1, j2) of an x face is
+    (y, z), of a y face (x, z), of a z face (x, y)."""
+    a = face // 2
+    return (ny, nx) if a == 2 else (nz, ny if a == 0 else nx)
+
+
+def face_value(inflow, face, x, y, z, nz):
+    """Boundary state of `face` at the face cell over (x, y, z) from
+    {face: [nz][3] profile or [n2][n1][3] per-cell array}: the array entry
+    of the cell's transverse coordinates, or the profile at its height (the
+    top row for the z+ face)."""
+    v = np.asarray(inflow[face], np.float64)
+    if v.ndim == 3:
+        a = face // 2
+        return v[(y, x) if a == 2 else (z, y if a == 0 else x)]
+    return v[nz - 1 if face == 5 else z]
 
 
 def _load():
@@ -131,9 +151,16 @@ class Oracle:
         self.solid = np.zeros(self.shape, np.uint8) if solid is None else \
             np.ascontiguousarray(solid, np.uint8).reshape(self.shape)
         self.inflow = np.zeros((6, nz, 3), np.float64)
+        self._face_base = {}
         if inflow is not None:
             for face, prof in inflow.items():
-                self.inflow[face] = np.asarray(prof, np.float64).reshape(nz, 3)
+                a = np.asarray(prof, np.float64)
+                if a.ndim == 3:   # per-cell boundary state of the face, [n2][n1][3]
+                    a = np.ascontiguousarray(a).reshape(face_shape(face, nx, ny, nz) + (3,))
+                    self._face_base[face] = a
+                    self.cfg.face_base[face] = a.ctypes.data
+                else:
+                    self.inflow[face] = a.reshape(nz, 3)
         self.lib = _load()
         self._field = None
 

@@ -88,6 +88,11 @@ typedef struct {
     double sponge_strength;     /* s_max of the sponge / buffer nudging (Sec. 2.2); 0: off */
     int32_t sponge_width;       /* W, layers next to each nudged face */
     int32_t pad_;
+    const double *face_base[6]; /* optional per-cell boundary velocity of each face (the
+                                   face-wise mapped boundary state, Sec. 2.3; App. F's U_b,i):
+                                   [n2][n1][3] over the face's cells, n1 = ny for x faces and nx
+                                   otherwise, n2 = ny for z faces and nz otherwise; NULL: the
+                                   face's per-height profile */
 } or_cfg;
 
 /* Error state of the last call (0 = fine). */
@@ -226,20 +231,29 @@ static int is_solid(const or_cfg *g, const uint8_t *solid, const int *p)
     return solid[IDX(g, p[0], p[1], p[2])] != 0;
 }
 
-/* Inflow velocity of an inflow cell: the profile of its face at its height z. */
+/* Boundary state of face `face` at the face cell with the transverse
+ * coordinates of p (its coordinate along the face normal is ignored): the
+ * per-cell face array when given, else the face's profile at the cell's
+ * height (the top row for the z+ face). */
+static const double *face_value(const or_cfg *g, const double *inflow, int face, const int *p)
+{
+    if (g->face_base[face]) {
+        int a = face / 2;
+        int64_t j = a == 0 ? p[1] + (int64_t)g->ny * p[2]
+                  : a == 1 ? p[0] + (int64_t)g->nx * p[2] : p[0] + (int64_t)g->nx * p[1];
+        return g->face_base[face] + 3 * j;
+    }
+    return inflow + ((int64_t)face * g->nz + (face == 5 ? g->nz - 1 : p[2])) * 3;
+}
+
+/* Inflow velocity of an inflow cell: the instantaneous per-cell field when
+ * given, else the boundary state of its face. */
 static void inflow_velocity(const or_cfg *g, const double *inflow, int face, const int *p, double *u)
 {
-    if (g->inflow_field) {
-        const double *v = g->inflow_field + 3 * IDX(g, p[0], p[1], p[2]);
-        u[0] = v[0];
-        u[1] = v[1];
-        u[2] = v[2];
-        return;
-    }
-    const double *row = inflow + ((int64_t)face * g->nz + p[2]) * 3;
-    u[0] = row[0];
-    u[1] = row[1];
-    u[2] = row[2];
+    const double *v = g->inflow_field ? g->inflow_field + 3 * IDX(g, p[0], p[1], p[2]) : face_value(g, inflow, face, p);
+    u[0] = v[0];
+    u[1] = v[1];
+    u[2] = v[2];
 }
 
 /* ------------------------------------------------------------------ */
@@ -395,7 +409,8 @@ static double sponge_at(const or_cfg *g, const int *p, int *face)
 /* Post-collision populations of one non-solid, non-inflow cell: the
  * collision, then the nudging toward the equilibrium of the face's target
  * velocity at the cell's density, f* += s (feq(rho, u_t) - feq(rho, u)),
- * with u_t the face's profile at the cell's height (the top row for z+). */
+ * with u_t the face's boundary state at the cell's projection onto the face
+ * (per-height profile: its value at the cell's height, the top row for z+). */
 void or_collide_cell(const or_cfg *g, const double *inflow, const double *fc, int x, int y, int z, double *fo)
 {
     double rho, u[3];
@@ -403,7 +418,7 @@ void or_collide_cell(const or_cfg *g, const double *inflow, const double *fc, in
     int p[3] = {x, y, z}, face;
     double s = sponge_at(g, p, &face);
     if (s > 0.0) {
-        const double *ut = inflow + ((int64_t)face * g->nz + (face == 5 ? g->nz - 1 : z)) * 3;
+        const double *ut = face_value(g, inflow, face, p);
         double et[NQ], e[NQ];
         or_equilibrium(rho, ut, et);
         or_equilibrium(rho, u, e);

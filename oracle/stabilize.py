@@ -22,15 +22,16 @@ cell near several faces takes the largest strength (the lower-numbered face
 on ties).  After the collision the populations move toward the equilibrium
 of the face's target velocity at the same density,
     f*_i += s (feq_i(rho, u_t) - feq_i(rho, u)),
-with u the velocity of the collision and u_t the face's profile at the
-cell's height (the top face's single row for the top sponge).  Mass is
+with u the velocity of the collision and u_t the face's boundary state at
+the cell's projection onto the face (a per-height profile: its value at the
+cell's height, the top face's single row for the top sponge).  Mass is
 unchanged and the momentum relaxes by s rho (u_t - u).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import INFLOW_EQ, equilibrium
+from . import INFLOW_EQ, equilibrium, face_value
 
 NORMALS_OUT = -np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float64)
 SPONGE_FACES = (0, 1, 2, 3, 5)
@@ -78,13 +79,17 @@ def balance_field(faces, solid, field):
 
 
 def net_flux_profiles(faces, solid, profiles):
+    """Phi of the boundary states {face: [nz][3] profile or [n2][n1][3] per-cell array}."""
     c = boundary_cells(faces, solid)
-    u = np.array([profiles[f][z] for f, x, y, z in c]).reshape(-1, 3)
+    nz = solid.shape[0]
+    u = np.array([face_value(profiles, f, x, y, z, nz) for f, x, y, z in c]).reshape(-1, 3)
     return float(np.sum(np.einsum("na,na->n", u, NORMALS_OUT[c[:, 0]]))), len(c)
 
 
 def balance_profiles(faces, solid, profiles):
-    """Same correction on the per-height profiles {face: [nz, 3]}."""
+    """Same correction on the boundary states of the faces {face: [nz, 3]
+    profile or [n2][n1][3] per-cell array}: every entry of a face moves by
+    -(Phi / N) n_out."""
     phi, n = net_flux_profiles(faces, solid, profiles)
     out = {f: np.array(p, np.float64, copy=True) for f, p in profiles.items()}
     if n == 0:
@@ -116,5 +121,7 @@ def nudge(fstar, rho, u, u_target, s):
     return fstar + s * (equilibrium(rho, u_target) - equilibrium(rho, u))
 
 
-def target_velocity(profiles, face, nz, z):
-    return np.asarray(profiles[face][nz - 1 if face == 5 else z], np.float64)
+def target_velocity(profiles, face, nz, z, x=0, y=0):
+    """Nudging target of `face` for the cell (x, y, z): the face's boundary
+    state at the cell's projection onto the face."""
+    return np.asarray(face_value(profiles, face, x, y, z, nz), np.float64)

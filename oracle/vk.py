@@ -43,7 +43,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import INFLOW_EQ, splitmix64
+from . import INFLOW_EQ, face_value, splitmix64
 
 NORMALS = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float64)
 VK_FACES = (0, 1, 2, 3, 5)     # the bottom face (z-) is never perturbed
@@ -79,7 +79,9 @@ def owner_face(faces, nx, ny, nz, x, y, z):
 
 
 def active_cells(faces, solid, profiles, p: VKParams):
-    """Step 1-3.  Returns (cells [n, 4] = face, x, y, z; U_b [n, 3]; u_ref; e_c)."""
+    """Step 1-3.  profiles: {face: [nz][3] per-height profile or [n2][n1][3]
+    per-cell boundary state}, the mean boundary velocity U_b,i of each cell.
+    Returns (cells [n, 4] = face, x, y, z; U_b [n, 3]; u_ref; e_c)."""
     nz, ny, nx = solid.shape
     rows = []
     for z in range(nz):
@@ -90,7 +92,7 @@ def active_cells(faces, solid, profiles, p: VKParams):
                 f = owner_face(faces, nx, ny, nz, x, y, z)
                 if f < 0 or f not in VK_FACES:
                     continue
-                ub = np.asarray(profiles[f][z], np.float64)
+                ub = np.asarray(face_value(profiles, f, x, y, z, nz), np.float64)
                 if p.inflow_only and not ub @ NORMALS[f] > 0.0:
                     continue
                 rows.append((f, x, y, z, ub))
@@ -194,7 +196,8 @@ class VonKarmanInflow:
         return (1.0 - al) * self.q(ta) + al * self.q(ta + s)
 
     def field(self, t: int) -> np.ndarray:
-        """[nz, ny, nx, 3]: U_b at every inflow cell, U_b + sigma q at active ones."""
+        """[nz, ny, nx, 3]: U_b at every inflow cell (its face's boundary
+        state), U_b + sigma q at active ones."""
         nz, ny, nx = self.solid.shape
         out = np.zeros((nz, ny, nx, 3))
         for f, prof in self.profiles.items():
@@ -204,7 +207,7 @@ class VonKarmanInflow:
                 for y in range(ny):
                     for x in range(nx):
                         if owner_face(self.faces, nx, ny, nz, x, y, z) == f:
-                            out[z, y, x] = prof[z]
+                            out[z, y, x] = face_value(self.profiles, f, x, y, z, nz)
         if len(self.cells):
             v = self.ub + self.sigma[:, None] * self.q_strided(t)
             c = self.cells
