@@ -92,12 +92,28 @@ typedef struct {
  * NULL on error and lbm_last_error(NULL) gives the message. */
 int lbm_create(const lbm_grid *grid, const uint8_t *solid, const lbm_params *params, lbm_ctx **out);
 
-/* Set the velocity profile of an INFLOW_EQ face: host double [nz][3]; a cell
- * of the face layer at height z takes feq(rho0, u[z]) (Sec. 3: equilibrium
- * velocity boundaries; App. F: the boundary velocity array).  A cell on two
- * inflow faces takes the profile of the lower-numbered face.  Takes effect at
- * the next step.  Errors: EINVAL (face not INFLOW_EQ, NULL u). */
+/* Set the velocity profile of an INFLOW_EQ face: host double [nz][3]; every
+ * cell of the face layer at height z gets the boundary state u[z] (the z+
+ * face: u[nz - 1]), so an inflow cell there takes feq(rho0, u[z]) (Sec. 3:
+ * equilibrium velocity boundaries; App. F: the boundary velocity array).  A
+ * cell on two inflow faces takes the state of the lower-numbered face.
+ * Replaces the face's states set by either call.  Takes effect at the next
+ * step.  Errors: EINVAL (face not INFLOW_EQ, NULL u, non-finite value). */
 int lbm_set_inflow(lbm_ctx *ctx, int32_t face, const double *u);
+
+/* Set the boundary state of every cell of an INFLOW_EQ face (Sec. 2.3: the
+ * boundary states come from a face-wise mapping of the mesoscale field onto
+ * the faces; App. F: the mean boundary velocity U_b,i of each cell).  u: host
+ * double [n2][n1][3], cell (j1, j2) of the face being (y, z) on the x faces,
+ * (x, z) on the y faces and (x, y) on the z faces, n1 and n2 their extents;
+ * copied.  The entry of a cell that is solid or belongs to a lower-numbered
+ * inflow face is kept but only read as a sponge target.  The state is what
+ * the inflow cells impose (feq(rho0, u)), the sponge / buffer layers relax
+ * toward (at each cell's projection onto the face), flux balancing (mode 1)
+ * corrects and the synthetic turbulence fluctuates around.  Takes effect at
+ * the next step.  Errors: EINVAL (face not INFLOW_EQ, NULL u, non-finite
+ * value). */
+int lbm_set_inflow_face(lbm_ctx *ctx, int32_t face, const double *u);
 
 /* Set the rotation vector Omega of the frame in lattice units (App. E:
  * Omega_lbm = Omega_SI * dt_SI, for the Earth Omega_SI = 7.292115e-5 rad/s
@@ -116,7 +132,7 @@ int lbm_set_rotation(lbm_ctx *ctx, const double *omega);
  * time t the boundary velocity of each active cell becomes
  *   U_i(t) = U_b,i + sigma_i q(x_i, t),
  *   q_a(x, t) = sum_m A_m,a cos(k_m . x - omega_m t + phi_m,a),
- * with U_b,i the face's per-height profile (lbm_set_inflow) and x the global
+ * with U_b,i the cell's boundary state (lbm_set_inflow, lbm_set_inflow_face) and x the global
  * lattice coordinates of the cell (origin + index), so grids that tile one
  * domain see one field.  Active cells: cells of the INFLOW_EQ faces x-, x+,
  * y-, y+, z+ (never z-), not solid, on one face each (the lower-numbered
@@ -162,8 +178,9 @@ int lbm_set_turbulence(lbm_ctx *ctx, const lbm_turbulence *p);
  * face layer gets s = strength ((width + 1 - d) / width)^2 (the largest over
  * the faces, the lower-numbered face on ties), and after its collision
  *   f*_i += s (feq_i(rho, u_t) - feq_i(rho, u)),
- * with rho, u the cell's collision moments and u_t the face's profile at the
- * cell's height (the z+ face: its single row).  Mass is unchanged; the
+ * with rho, u the cell's collision moments and u_t the face's boundary state
+ * at the cell's projection onto the face (for a profile: its value at the
+ * cell's height; the z+ face: its single row).  Mass is unchanged; the
  * momentum relaxes by s rho (u_t - u).  Widths and strengths are not printed
  * in the paper; the ramp is this library's choice.  width 0 or strength 0
  * turns it off.  While it is on, lbm_adjoint_step returns ESTATE.
@@ -176,9 +193,10 @@ int lbm_set_sponge(lbm_ctx *ctx, int32_t width, double strength);
  * faces (each on its owning face) the net outward volume flux is
  * Phi = sum_i U_i . n_i; the least-squares smallest change of the normal
  * velocities that zeroes it is U_i -= (Phi / N) n_i for every cell.
- *   mode 1: apply it to the per-height profiles now (host, double); the
- *           synthetic-turbulence generator is rebuilt on the new profiles;
- *   mode 2: apply it to the whole per-cell boundary field (profiles plus
+ *   mode 1: apply it to the boundary states now (host, double): every entry
+ *           of every INFLOW_EQ face moves by -(Phi / N) n; the
+ *           synthetic-turbulence generator is rebuilt on the new states;
+ *   mode 2: apply it to the whole per-cell boundary field (states plus
  *           synthetic turbulence) now and on the device before every step;
  *   mode 0: stop the per-step balancing.
  * phi_before, phi_after (host, may be NULL): the net flux before and after
@@ -258,8 +276,8 @@ int lbm_set_stats(lbm_ctx *ctx, void *acc, int32_t stride);
 
 /* One step from a canonical state to a canonical state, out of place:
  * src, dst device store [19][N], distinct.  Uses the context's geometry,
- * parameters and inflow profiles; does not touch its state or time.  This is
- * the recompute step of the checkpointed adjoint. */
+ * parameters and inflow boundary states; does not touch its state or time.
+ * This is the recompute step of the checkpointed adjoint. */
 int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
 
 /* One discrete-adjoint step (transpose of the linearised update, eqs. D.2-D.4
@@ -269,12 +287,13 @@ int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
  * the local collision at the canonical state f_t (device store [19][N]).
  * lam_next, lam: device real [19][N] canonical layout, distinct.
  * probe_src: device real [np][3] = dL/du(x_p, t) for the registered probes,
- * or NULL.  g_inflow: device real [2][6][nz][3]; [0] += the gradient of the
- * loss with respect to each inflow face profile u_in(face, z) through the
- * step t -> t+1, as a compensated (Neumaier) sum with [1] the compensation.
- * Solid and inflow cells get lam = 0.  The face-shell and inflow-gradient
- * kernels run on an internal side stream forked from and joined back into
- * the context's stream, so the call stays ordered like any other call on it. */
+ * or NULL.  g_inflow: device real [2][6][nz][3], or NULL; [0] += the
+ * gradient of the loss with respect to each inflow face profile u_in(face, z)
+ * through the step t -> t+1 (the sum over the face's inflow cells at height z
+ * of the derivative with respect to their own velocity, i.e. with respect to
+ * a uniform shift of that row), as a compensated (Neumaier) sum with [1] the
+ * compensation.  Solid and inflow cells get lam = 0.  One kernel launch on
+ * the context's stream. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
                      const void *probe_src, void *g_inflow);
 

@@ -55,7 +55,8 @@ class _Turbulence(ctypes.Structure):
                 ("gain", ctypes.c_double * 3), ("origin", ctypes.c_double * 3), ("seed", ctypes.c_uint64)]
 
 
-EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_rotation", "lbm_set_turbulence",
+EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_inflow_face", "lbm_set_rotation",
+           "lbm_set_turbulence",
            "lbm_turbulence_info", "lbm_get_inflow", "lbm_set_sponge", "lbm_balance_flux", "lbm_net_flux",
            "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
@@ -79,6 +80,7 @@ def load(path: str = LIB_PATH):
         "lbm_create": ([ctypes.POINTER(_Grid), P, ctypes.POINTER(_Params), ctypes.POINTER(P)], ctypes.c_int),
         "lbm_destroy": ([P], None),
         "lbm_set_inflow": ([P, I32, P], ctypes.c_int),
+        "lbm_set_inflow_face": ([P, I32, P], ctypes.c_int),
         "lbm_set_rotation": ([P, P], ctypes.c_int),
         "lbm_set_turbulence": ([P, ctypes.POINTER(_Turbulence)], ctypes.c_int),
         "lbm_turbulence_info": ([P, P, P, P], ctypes.c_int),
@@ -188,8 +190,22 @@ class LBM:
             pass
 
     # -- ABI calls ----------------------------------------------------------
-    def set_inflow(self, face, profile):
-        prof = np.ascontiguousarray(profile, np.float64).reshape(self.nz, 3)
+    def face_shape(self, face):
+        """(n2, n1) of a face's per-cell arrays: cell (j1, j2) is (y, z) on the
+        x faces, (x, z) on the y faces, (x, y) on the z faces."""
+        a = int(face) // 2
+        return (self.ny, self.nx) if a == 2 else (self.nz, self.ny if a == 0 else self.nx)
+
+    def set_inflow(self, face, state):
+        """Boundary state of an INFLOW_EQ face: a per-height profile [nz, 3]
+        (lbm_set_inflow) or one velocity per face cell [n2, n1, 3]
+        (lbm_set_inflow_face, see face_shape)."""
+        a = np.asarray(state, np.float64)
+        if a.ndim == 3:
+            arr = np.ascontiguousarray(a).reshape(self.face_shape(face) + (3,))
+            self._check(self.lib.lbm_set_inflow_face(self.ctx, int(face), arr.ctypes.data_as(ctypes.c_void_p)))
+            return
+        prof = np.ascontiguousarray(a).reshape(self.nz, 3)
         self._check(self.lib.lbm_set_inflow(self.ctx, int(face), prof.ctypes.data_as(ctypes.c_void_p)))
 
     def set_rotation(self, omega):
@@ -234,7 +250,7 @@ class LBM:
         self._check(self.lib.lbm_set_sponge(self.ctx, int(width), float(strength)))
 
     def balance_flux(self, mode):
-        """Global flux balancing: 1 profiles now, 2 the full field every step, 0 off.
+        """Global flux balancing: 1 the boundary states now, 2 the full field every step, 0 off.
         Returns (phi_before, phi_after)."""
         a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
         self._check(self.lib.lbm_balance_flux(self.ctx, int(mode), ctypes.byref(a), ctypes.byref(b)))

@@ -378,14 +378,16 @@ __device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__
     for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = solid_lane ? R(0) : ls[j];
 }
 
-// dL/du_in(face F, height z): one block per (F, z), a fixed-order tree over
-// the face's inflow cells at that height, then a compensated (Neumaier)
+// dL/du_in(face F, height z): the sum over the face's inflow cells at that
+// height of lam*_k d feq_k/du at each cell's own inflow velocity (the
+// derivative with respect to a shift of the whole row).  One block per
+// (F, z), a fixed-order tree over the cells, then a compensated (Neumaier)
 // update of g[0] (sum) and g[1] (compensation).
 constexpr int ADJ_RED = 256;
 
 template <int K>
 __device__ inline void adjoint_inflow(const typename Codec<K>::real* __restrict__ lam_next,
-                                      const uint64_t* __restrict__ mask, const double* __restrict__ prof,
+                                      const uint64_t* __restrict__ mask, const double* __restrict__ uin,
                                       const Geo& g, const Phys<typename Codec<K>::real>& P, int F, int zz,
                                       typename Codec<K>::real* gacc)
 {
@@ -397,19 +399,14 @@ __device__ inline void adjoint_inflow(const typename Codec<K>::real* __restrict_
     else if (a == 1) count = g.nx;
     else count = ((F & 1) ? g.nz - 1 : 0) == zz ? (long long)g.nx * g.ny : 0;
     R acc[3] = {R(0), R(0), R(0)};
-    R ux, uy, uz;
-    {
-        const double* p = prof + ((long long)F * g.nz + zz) * 3;
-        ux = R(p[0]);
-        uy = R(p[1]);
-        uz = R(p[2]);
-    }
     for (long long t = threadIdx.x; t < count; t += ADJ_RED) {
         int x, y, z = zz;
         if (a == 0) { x = (F & 1) ? g.nx - 1 : 0; y = (int)t; }
         else if (a == 1) { y = (F & 1) ? g.ny - 1 : 0; x = (int)t; }
         else { x = (int)(t % g.nx); y = (int)(t / g.nx); }
         if (solid_at(mask, g, x, y, z) || inflow_face_of(g, x, y, z) != F) continue;
+        R ux, uy, uz;   // the cell's own inflow velocity
+        load_inflow<R>(uin, g, F, x, y, z, ux, uy, uz);
         adj_static_for<0, NQ>([&](auto ic) {
             constexpr int k = decltype(ic)::value;
             constexpr V3 c = dirv(k);
@@ -454,7 +451,7 @@ template <int K>
 __global__ void __launch_bounds__(256, K == 0 ? 3 : 4)
 k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec<K>::real* __restrict__ lam_next,
           typename Codec<K>::real* __restrict__ lam, const uint64_t* __restrict__ mask,
-          const double* __restrict__ prof, Geo g, Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab,
+          const double* __restrict__ uin, Geo g, Phys<typename Codec<K>::real> P, const StepOff* __restrict__ otab,
           long long nwaves, const unsigned* __restrict__ cells, long long ncells, const unsigned* __restrict__ sched,
           typename Codec<K>::real* gacc, AdjProbes pr)
 {
@@ -476,7 +473,7 @@ k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec
         int F = 0;
         for (int seen = 0; F < 6; F++)
             if (g.face[F] == F_INFLOW && seen++ == k) break;
-        adjoint_inflow<K>(lam_next, mask, prof, g, P, F, zz, gacc);
+        adjoint_inflow<K>(lam_next, mask, uin, g, P, F, zz, gacc);
         return;
     }
     const long long wave = (long long)b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -495,7 +492,7 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
     AdjProbes pr = d.probes;
     pr.src = pr.n > 0 ? probe_src : nullptr;
     hipLaunchKernelGGL((k_adjoint<K>), dim3(d.adj_sched_n), dim3(256), 0, s, (const typename C::store*)f_t,
-                       (const R*)lam_next, (R*)lam, d.mask, d.prof, g, phys_of<K>(d), d.off_adj, nwaves, d.adj_list,
+                       (const R*)lam_next, (R*)lam, d.mask, d.uin, g, phys_of<K>(d), d.off_adj, nwaves, d.adj_list,
                        d.adj_list_n, d.adj_sched, (R*)g_inflow, pr);
     return hipGetLastError();
 }

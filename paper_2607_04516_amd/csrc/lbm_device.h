@@ -173,7 +173,7 @@ struct Phys {
     int has_force; // F != 0 or has_rot: the Guo source is applied
     int sponge_w;  // width W of the sponge / buffer layers; 0: off
     R sponge_s;    // strength s_max at the layer next to the face
-    const double* target;  // per-height face profiles [6][nz][3]: the nudging targets
+    const double* target;  // per-cell boundary states of the INFLOW_EQ faces (inflow_slot): the nudging targets
 };
 
 // Body force on one cell: the uniform force plus the Coriolis force of the
@@ -562,7 +562,8 @@ __device__ inline void nudge_at(R* h, const Phys<R>& P, const Geo& g, int x, int
         }
     }
     if (face < 0) return;
-    const double* pt = P.target + ((long long)face * g.nz + (face == 5 ? g.nz - 1 : z)) * 3;
+    // the face's boundary state at the cell's projection onto the face
+    const double* pt = P.target + 3 * inflow_slot(g, face, x, y, z);
     const R tx = R(pt[0]), ty = R(pt[1]), tz = R(pt[2]);
     const R k = best * R(SC) * (P.rho0 + drho);
     const R dus = R(-1.5) * ((tx * tx + ty * ty + tz * tz) - (ux * ux + uy * uy + uz * uz));

@@ -28,7 +28,7 @@ struct DevCtx {
     void* f;              // in-place population array [19][nz][ny][pitch]
     const uint64_t* mask; // solid bits [nz][ny][wpr]
     void* ghost;          // outflow ghost entries
-    const double* prof;   // inflow profiles [6][nz][3] (the per-height base velocities)
+    const double* ubase;  // per-cell boundary states of the INFLOW_EQ faces (inflow_slot): sponge targets
     const double* uin;    // per-cell inflow velocities (inflow_slot); what the step kernels read
     const unsigned* odd_list;  // waves of the odd step left to the general kernel
     long long odd_list_n;
@@ -69,7 +69,7 @@ static inline Phys<typename Codec<K>::real> phys_of(const DevCtx& d)
     P.has_force = (P.has_rot || d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
     P.sponge_w = d.sponge_s > 0.0 ? d.sponge_w : 0;
     P.sponge_s = R(d.sponge_s);
-    P.target = d.prof;
+    P.target = d.ubase;
     return P;
 }
 

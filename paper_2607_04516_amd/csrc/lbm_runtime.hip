@@ -28,9 +28,9 @@ struct lbm_ctx {
     void* f = nullptr;
     uint64_t* mask = nullptr;
     void* ghost = nullptr;
-    double* prof = nullptr; // device [6][nz][3]
-    std::vector<double> prof_host;
-    double* uin = nullptr;  // device per-cell inflow velocities [n_in][3] (inflow_slot)
+    double* ubase = nullptr;  // device per-cell boundary states of the INFLOW_EQ faces [n_in][3] (inflow_slot)
+    std::vector<double> base_host;  // host copy of ubase
+    double* uin = nullptr;  // device per-cell inflow velocities [n_in][3]: ubase plus turbulence / flux shift
     long long n_in = 0;
     std::vector<uint64_t> bits_host;  // solid bits, kept for the turbulence generator
     VkGen* vk = nullptr;              // synthetic inflow generator, NULL when off
@@ -149,7 +149,7 @@ static void free_all(lbm_ctx* c)
     c->ev_used = 0;
     vk_destroy(c->vk);
     c->vk = nullptr;
-    void* ptrs[] = {c->f, c->mask, c->ghost, c->prof, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
+    void* ptrs[] = {c->f, c->mask, c->ghost, c->ubase, c->u0, c->probes, c->red_partial, c->red_out, c->odd_list,
                     c->push_list, c->adj_list, c->push_sched, c->adj_sched, c->uin, c->flux_cells, c->flux_red, c->wave_idx, c->wave_tab, c->offsets,
                     c->probe_tab};
     for (void* q : ptrs)
@@ -157,7 +157,7 @@ static void free_all(lbm_ctx* c)
     c->f = nullptr;
     c->mask = nullptr;
     c->ghost = nullptr;
-    c->prof = nullptr;
+    c->ubase = nullptr;
     c->u0 = nullptr;
     c->probes = nullptr;
     c->probe_tab = nullptr;
@@ -336,7 +336,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     if ((rc = device_alloc(c, &c->f, pop_bytes, "populations")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->mask, bits.size() * sizeof(uint64_t), "mask")) != LBM_OK ||
         (rc = device_alloc(c, &c->ghost, (size_t)goff * c->store_bytes, "ghost planes")) != LBM_OK ||
-        (rc = device_alloc(c, (void**)&c->prof, 18 * (size_t)g.nz * sizeof(double), "profiles")) != LBM_OK ||
+        (rc = device_alloc(c, (void**)&c->ubase, 3 * (size_t)c->n_in * sizeof(double), "boundary states")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->u0, 3 * (size_t)g.nz * sizeof(double), "u0")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->uin, 3 * (size_t)c->n_in * sizeof(double), "inflow velocities")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->red_partial, 5 * (size_t)mass_blocks(g) * sizeof(double), "reduction")) !=
@@ -418,9 +418,9 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         c->d.adj_sched = c->adj_sched;
         c->d.adj_sched_n = (unsigned)sa.size();
     }
-    c->prof_host.assign(18 * (size_t)g.nz, 0.0);
+    c->base_host.assign(3 * (size_t)c->n_in, 0.0);
     hipError_t e = hipMemcpy(c->mask, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(c->prof, 0, 18 * (size_t)g.nz * sizeof(double));
+    if (e == hipSuccess && c->n_in) e = hipMemset(c->ubase, 0, 3 * (size_t)c->n_in * sizeof(double));
     if (e == hipSuccess && c->n_in) e = hipMemset(c->uin, 0, 3 * (size_t)c->n_in * sizeof(double));
     if (e == hipSuccess) e = hipMemset(c->f, 0, pop_bytes);
     if (e == hipSuccess && goff) e = hipMemset(c->ghost, 0, (size_t)goff * c->store_bytes);
@@ -433,7 +433,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->d.f = c->f;
     c->d.mask = c->mask;
     c->d.ghost = c->ghost;
-    c->d.prof = c->prof;
+    c->d.ubase = c->ubase;
     c->d.uin = c->uin;
     c->bits_host = std::move(bits);
     if ((rc = build_wave_masks(c)) != LBM_OK) {
@@ -483,23 +483,32 @@ int lbm_set_stream(lbm_ctx* c, void* s)
     return LBM_OK;
 }
 
-// Fill the per-cell inflow velocities of one face from its height profile.
-static int broadcast_profile(lbm_ctx* c, int F)
+// Copy the boundary states of face F (host) into ubase and uin (device).
+static int upload_base(lbm_ctx* c, int F)
 {
     const Geo& g = c->d.g;
     if (g.in_off[F] < 0) return LBM_OK;
-    const long long area = face_cells_host(g, F);
-    const int a = F >> 1;
-    const long long n1 = a == 0 ? g.ny : g.nx;
-    std::vector<double> h(3 * (size_t)area);
-    for (long long j = 0; j < area; j++) {
-        const long long j2 = j / n1;   // z for x and y faces, y for z faces
-        const int z = a == 2 ? (F & 1 ? g.nz - 1 : 0) : (int)j2;
-        for (int k = 0; k < 3; k++) h[3 * j + k] = c->prof_host[((size_t)F * g.nz + z) * 3 + k];
-    }
-    HIPCHK(c, hipMemcpyAsync(c->uin + 3 * g.in_off[F], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
-                             c->stream), "upload inflow velocities");
-    HIPCHK(c, hipStreamSynchronize(c->stream), "upload inflow velocities");
+    const size_t off = 3 * (size_t)g.in_off[F], n = 3 * (size_t)face_cells_host(g, F);
+    HIPCHK(c, hipMemcpyAsync(c->ubase + off, c->base_host.data() + off, n * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream), "upload boundary states");
+    HIPCHK(c, hipMemcpyAsync(c->uin + off, c->ubase + off, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+           "upload boundary states");
+    // the host copy must stay valid until the copy ran
+    HIPCHK(c, hipStreamSynchronize(c->stream), "upload boundary states");
+    return LBM_OK;
+}
+
+// After the boundary states changed: rebuild the synthetic-inflow generator
+// (its mean field, sigma and u_ref follow them).
+static int refresh_turbulence(lbm_ctx* c)
+{
+    if (!c->vk) return LBM_OK;
+    VkGen* v = nullptr;
+    std::string err;
+    int rc = vk_create(&v, c->vkp, c->d.g, c->bits_host, c->base_host, err);
+    if (rc != LBM_OK) return fail(c, rc, err);
+    vk_destroy(c->vk);
+    c->vk = v;
     return LBM_OK;
 }
 
@@ -508,28 +517,37 @@ int lbm_set_inflow(lbm_ctx* c, int32_t face, const double* u)
     if (!c) return LBM_EINVAL;
     if (face < 0 || face > 5 || !u) return fail(c, LBM_EINVAL, "bad face or NULL profile");
     if (c->d.g.face[face] != LBM_INFLOW_EQ) return fail(c, LBM_EINVAL, "face is not an INFLOW_EQ face");
-    const int nz = c->d.g.nz;
-    for (int i = 0; i < 3 * nz; i++) {
+    const Geo& g = c->d.g;
+    for (int i = 0; i < 3 * g.nz; i++)
         if (!std::isfinite(u[i])) return fail(c, LBM_EINVAL, "non-finite inflow velocity");
-        c->prof_host[(size_t)face * 3 * nz + i] = u[i];
+    // every cell of the face takes the profile at its height (the top row for z+)
+    const int a = face >> 1;
+    const long long n1 = a == 0 ? g.ny : g.nx, area = face_cells_host(g, face);
+    double* dst = c->base_host.data() + 3 * (size_t)g.in_off[face];
+    for (long long j = 0; j < area; j++) {
+        const int z = a == 2 ? ((face & 1) ? g.nz - 1 : 0) : (int)(j / n1);
+        for (int k = 0; k < 3; k++) dst[3 * j + k] = u[3 * z + k];
     }
-    HIPCHK(c, hipMemcpyAsync(c->prof + (size_t)face * 3 * nz, c->prof_host.data() + (size_t)face * 3 * nz,
-                             3 * (size_t)nz * sizeof(double), hipMemcpyHostToDevice, c->stream),
-           "upload inflow profile");
-    // the host copy must stay valid until the copy ran
-    HIPCHK(c, hipStreamSynchronize(c->stream), "upload inflow profile");
     c->prof_set[face] = true;
-    int rc = broadcast_profile(c, face);
+    int rc = upload_base(c, face);
     if (rc != LBM_OK) return rc;
-    if (c->vk) {   // the generator's mean field, sigma and u_ref follow the profiles
-        VkGen* v = nullptr;
-        std::string err;
-        rc = vk_create(&v, c->vkp, c->d.g, c->bits_host, c->prof_host, err);
-        if (rc != LBM_OK) return fail(c, rc, err);
-        vk_destroy(c->vk);
-        c->vk = v;
-    }
-    return LBM_OK;
+    return refresh_turbulence(c);
+}
+
+int lbm_set_inflow_face(lbm_ctx* c, int32_t face, const double* u)
+{
+    if (!c) return LBM_EINVAL;
+    if (face < 0 || face > 5 || !u) return fail(c, LBM_EINVAL, "bad face or NULL boundary states");
+    if (c->d.g.face[face] != LBM_INFLOW_EQ) return fail(c, LBM_EINVAL, "face is not an INFLOW_EQ face");
+    const Geo& g = c->d.g;
+    const long long n = 3 * face_cells_host(g, face);
+    for (long long i = 0; i < n; i++)
+        if (!std::isfinite(u[i])) return fail(c, LBM_EINVAL, "non-finite inflow velocity");
+    std::copy(u, u + n, c->base_host.begin() + 3 * (size_t)g.in_off[face]);
+    c->prof_set[face] = true;
+    int rc = upload_base(c, face);
+    if (rc != LBM_OK) return rc;
+    return refresh_turbulence(c);
 }
 
 int lbm_set_rotation(lbm_ctx* c, const double* omega)
@@ -549,12 +567,12 @@ int lbm_set_turbulence(lbm_ctx* c, const lbm_turbulence* p)
     VkGen* v = nullptr;
     if (p) {
         std::string err;
-        int rc = vk_create(&v, *p, c->d.g, c->bits_host, c->prof_host, err);
+        int rc = vk_create(&v, *p, c->d.g, c->bits_host, c->base_host, err);
         if (rc != LBM_OK) return fail(c, rc, err);
     }
-    // back to the profiles everywhere; the generator writes its cells at the next step
+    // back to the boundary states everywhere; the generator writes its cells at the next step
     for (int F = 0; F < 6; F++) {
-        int rc = broadcast_profile(c, F);
+        int rc = upload_base(c, F);
         if (rc != LBM_OK) {
             vk_destroy(v);
             return rc;
@@ -606,8 +624,8 @@ static int build_flux_cells(lbm_ctx* c)
     return LBM_OK;
 }
 
-// Net outward flux of the per-height profiles over the boundary cells.
-static double profile_flux(const lbm_ctx* c, long long* count)
+// Net outward flux of the boundary states over the boundary cells.
+static double base_flux(const lbm_ctx* c, long long* count)
 {
     const Geo& g = c->d.g;
     double phi = 0.0;
@@ -618,7 +636,7 @@ static double profile_flux(const lbm_ctx* c, long long* count)
                 const int F = inflow_face_of(g, x, y, z);
                 if (F < 0) continue;
                 if ((c->bits_host[((size_t)y + (size_t)g.ny * z) * g.wpr + (x >> 6)] >> (x & 63)) & 1ull) continue;
-                const double v = c->prof_host[((size_t)F * g.nz + z) * 3 + (F >> 1)];
+                const double v = c->base_host[3 * (size_t)inflow_slot(g, F, x, y, z) + (F >> 1)];
                 phi += (F & 1) ? v : -v;
                 n++;
             }
@@ -657,30 +675,20 @@ int lbm_balance_flux(lbm_ctx* c, int32_t mode, double* phi_before, double* phi_a
     }
     if (mode == 1) {
         long long n = 0;
-        const double phi = profile_flux(c, &n);
+        const double phi = base_flux(c, &n);
         if (phi_before) *phi_before = phi;
         if (n > 0) {
+            // every entry of every INFLOW_EQ face moves by -(phi / n) n_out
             const double delta = phi / (double)n;
             for (int F = 0; F < 6; F++) {
                 if (g.face[F] != LBM_INFLOW_EQ) continue;
-                for (int z = 0; z < g.nz; z++)
-                    c->prof_host[((size_t)F * g.nz + z) * 3 + (F >> 1)] -= (F & 1) ? delta : -delta;
+                double* b = c->base_host.data() + 3 * (size_t)g.in_off[F];
+                for (long long j = 0; j < face_cells_host(g, F); j++) b[3 * j + (F >> 1)] -= (F & 1) ? delta : -delta;
+                if ((rc = upload_base(c, F)) != LBM_OK) return rc;
             }
-            HIPCHK(c, hipMemcpyAsync(c->prof, c->prof_host.data(), 18 * (size_t)g.nz * sizeof(double),
-                                     hipMemcpyHostToDevice, c->stream), "upload profiles");
-            HIPCHK(c, hipStreamSynchronize(c->stream), "upload profiles");
-            for (int F = 0; F < 6; F++)
-                if ((rc = broadcast_profile(c, F)) != LBM_OK) return rc;
-            if (c->vk) {
-                VkGen* v = nullptr;
-                std::string err;
-                rc = vk_create(&v, c->vkp, c->d.g, c->bits_host, c->prof_host, err);
-                if (rc != LBM_OK) return fail(c, rc, err);
-                vk_destroy(c->vk);
-                c->vk = v;
-            }
+            if ((rc = refresh_turbulence(c)) != LBM_OK) return rc;
         }
-        if (phi_after) *phi_after = profile_flux(c, nullptr);
+        if (phi_after) *phi_after = base_flux(c, nullptr);
         return LBM_OK;
     }
     // mode 2: balance the current field now, and before every step from now on

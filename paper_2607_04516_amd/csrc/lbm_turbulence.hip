@@ -127,7 +127,7 @@ void vk_destroy(VkGen* v)
 }
 
 int vk_create(VkGen** out, const lbm_turbulence& p, const Geo& g, const std::vector<uint64_t>& bits,
-              const std::vector<double>& prof, std::string& err)
+              const std::vector<double>& base, std::string& err)
 {
     *out = nullptr;
     if (p.n_modes < 1 || p.n_modes > VK_MAX_MODES) {
@@ -160,7 +160,7 @@ int vk_create(VkGen** out, const lbm_turbulence& p, const Geo& g, const std::vec
                 const int z = a == 2 ? fixed : j2;
                 if (solid_host(bits, g, x, y, z) || inflow_face_of(g, x, y, z) != F) continue;
                 HostCell c{F, x, y, z, {0, 0, 0}};
-                for (int k = 0; k < 3; k++) c.ub[k] = prof[((size_t)F * g.nz + z) * 3 + k];
+                for (int k = 0; k < 3; k++) c.ub[k] = base[3 * (size_t)inflow_slot(g, F, x, y, z) + k];
                 if (p.inflow_only && !(dot_n(c.ub, F) > 0.0)) continue;
                 cand.push_back(c);
             }
