@@ -471,8 +471,9 @@ k_adjoint(const typename Codec<K>::store* __restrict__ f_t, const typename Codec
         const int k = (int)(b / (unsigned)g.nz);
         const int zz = (int)(b % (unsigned)g.nz);
         int F = 0;
-        for (int seen = 0; F < 6; F++)
-            if (g.face[F] == F_INFLOW && seen++ == k) break;
+#pragma unroll
+        for (int q = 0, seen = 0; q < 6; q++)
+            if (g.face[q] == F_INFLOW && seen++ == k) F = q;
         adjoint_inflow<K>(lam_next, mask, uin, g, P, F, zz, gacc);
         return;
     }
@@ -491,7 +492,18 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
     const long long nwaves = (long long)g.ncx * g.ny * g.nz;
     AdjProbes pr = d.probes;
     pr.src = pr.n > 0 ? probe_src : nullptr;
-    hipLaunchKernelGGL((k_adjoint<K>), dim3(d.adj_sched_n), dim3(256), 0, s, (const typename C::store*)f_t,
+    // Four blocks (16 waves) resident per CU: measured fastest for the 32-bit
+    // adjoint (with five or more, the waves' gathers of lam(t+1) and loads of
+    // f(t) evict each other's lines; with three, latency is exposed).  The
+    // registers allow five, so the launch requests enough LDS to leave room
+    // for four.  FP64 needs registers for fewer than four anyway.
+    size_t lds = 0;
+    if (K != 0 && d.lds_per_cu > 0) {
+        const size_t stat = 3 * ADJ_RED * sizeof(R);   // the inflow blocks' reduction buffer
+        const size_t quarter = (size_t)d.lds_per_cu / 4 / 1024 * 1024;
+        if (quarter > stat + 1024) lds = quarter - stat;
+    }
+    hipLaunchKernelGGL((k_adjoint<K>), dim3(d.adj_sched_n), dim3(256), lds, s, (const typename C::store*)f_t,
                        (const R*)lam_next, (R*)lam, d.mask, d.uin, g, phys_of<K>(d), d.off_adj, nwaves, d.adj_list,
                        d.adj_list_n, d.adj_sched, (R*)g_inflow, pr);
     return hipGetLastError();

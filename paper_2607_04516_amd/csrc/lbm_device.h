@@ -142,6 +142,17 @@ struct Geo {
     long long in_off[6];     // first per-cell inflow entry of each INFLOW_EQ face (-1: none)
 };
 
+// Entry i of a six-entry Geo array for a runtime i, as a select chain.  Where
+// a kernel indexes a kernel-argument array with a runtime index the compiler
+// may copy the whole Geo into scratch memory in every thread; which form
+// avoids that depends on the call site (the build test checks the hot
+// kernels for scratch).
+template <typename T>
+__host__ __device__ inline T pick6(const T (&v)[6], int i)
+{
+    return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : i == 3 ? v[3] : i == 4 ? v[4] : v[5];
+}
+
 // Per-cell inflow velocities (the boundary velocity array): three doubles
 // per cell of every INFLOW_EQ face, faces stacked from x- to z+; an x face is
 // indexed y + ny z, a y face x + nx z, a z face x + nx y.
@@ -149,7 +160,7 @@ __host__ __device__ inline long long inflow_slot(const Geo& g, int F, int x, int
 {
     const int a = F >> 1;
     const long long j = a == 0 ? y + (long long)g.ny * z : a == 1 ? x + (long long)g.nx * z : x + (long long)g.nx * y;
-    return g.in_off[F] + j;
+    return pick6(g.in_off, F) + j;
 }
 
 template <typename R>
@@ -269,7 +280,7 @@ __device__ inline Res resolve_plain(const Geo& g, const uint64_t* __restrict__ m
         const int n = dimn(g, a);
         const bool lo = (s[a] < 0), hi = (s[a] >= n);
         if (!(lo || hi)) continue;
-        const int kind = g.face[lo ? 2 * a : 2 * a + 1];
+        const int kind = lo ? g.face[2 * a] : g.face[2 * a + 1];
         if (kind == F_WALL) {
             return r;
         } else if (kind == F_PERIODIC) {

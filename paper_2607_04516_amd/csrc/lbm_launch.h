@@ -50,6 +50,7 @@ struct DevCtx {
     int sponge_w;         // sponge / buffer layer width; 0: off
     double sponge_s;      // its strength s_max
     AdjProbes probes;     // registered probes (src unset)
+    int lds_per_cu;       // bytes of LDS per compute unit (0: unknown)
 };
 
 // Collision parameters of a context in the codec's arithmetic type.

@@ -277,6 +277,12 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         delete c;
         return fail(nullptr, LBM_EHIP, "no HIP device");
     }
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess)
+            lds = 0;
+        c->d.lds_per_cu = lds;
+    }
 
     Geo& g = c->d.g;
     g.nx = grid->nx;
