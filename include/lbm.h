@@ -58,7 +58,10 @@ enum lbm_face_kind {
     LBM_INFLOW_EQ = 1,  /* the face layer holds feq(rho0, u_in(z)) cells */
     LBM_OUTFLOW_ZG = 2, /* zero-gradient: entering populations copy the inner layer */
     LBM_FREESLIP = 3,   /* specular reflection at the half plane outside the face */
-    LBM_WALL = 4        /* halfway bounce-back at the half plane outside the face */
+    LBM_WALL = 4,       /* halfway bounce-back at the half plane outside the face */
+    LBM_HALO = 5        /* y faces only: the face row is a ghost row holding a copy of the
+                           neighbouring slab's boundary row (slab decomposition along y);
+                           see lbm_halo_pack / lbm_halo_unpack */
 };
 
 enum lbm_face { LBM_XM = 0, LBM_XP = 1, LBM_YM = 2, LBM_YP = 3, LBM_ZM = 4, LBM_ZP = 5 };
@@ -296,6 +299,31 @@ int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
  * the context's stream. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
                      const void *probe_src, void *g_inflow);
+
+/* Halo exchange of a slab decomposition along y (one context per slab, the
+ * decomposition of the paper's multi-GPU runs).  A slab has a ghost row on
+ * each LBM_HALO side (y = 0 for y-, y = ny - 1 for y+) that mirrors the
+ * neighbour's boundary row; the kernels update ghost rows like free-slip
+ * face rows, and two exchanges keep the real rows exact: only the five
+ * populations with c_y toward the neighbour cross an interface.
+ *   After an even step (A-A swapped layout): the post-collision values of the
+ *   real boundary row moving toward the neighbour fill the neighbour's ghost
+ *   row, which its odd step gathers from.
+ *   After an odd step: the values this slab's odd step pushed into its ghost
+ *   row go back into the neighbour's real boundary row (where the pull there
+ *   came from a non-solid ghost cell).
+ * lbm_halo_pack writes what this context sends through `side` (0: y-, 1: y+)
+ * at its current phase; lbm_halo_unpack writes what the neighbour on `side`
+ * sent.  buf: device store [5][nz][nx] (directions with c_y = -1 for a y-
+ * send, +1 for a y+ send, ascending).  Call both after every step, all packs
+ * of the step before any unpack, and only between steps of all slabs in
+ * lockstep; the state then equals the undecomposed run's, bit for bit.  Ghost
+ * rows are counted by the diagnostics (mass, macros).  Contexts with a HALO
+ * face refuse the push step, the adjoint, the synthetic inflow and flux
+ * balancing (they would need quantities summed over all slabs).
+ * Errors: EINVAL (side not a HALO face, NULL buf). */
+int lbm_halo_pack(lbm_ctx *ctx, int32_t side, void *buf);
+int lbm_halo_unpack(lbm_ctx *ctx, int32_t side, const void *buf);
 
 /* Kernel timing for measurement: while enabled, a pair of HIP events on the
  * context's stream brackets every launch of the fused collide-and-stream

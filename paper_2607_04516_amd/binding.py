@@ -22,7 +22,7 @@ REAL_DTYPE = {F64: torch.float64, F32: torch.float32, F16S: torch.float32, BF16S
 # binary16 storage holds 256 * h (power-of-two scale into the normal range)
 STORE_SCALE = {F64: 1.0, F32: 1.0, F16S: 256.0, BF16S: 1.0}
 
-FACE_KIND = {"periodic": 0, "inflow": 1, "outflow": 2, "freeslip": 3, "wall": 4}
+FACE_KIND = {"periodic": 0, "inflow": 1, "outflow": 2, "freeslip": 3, "wall": 4, "halo": 5}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSTABLE", -5: "ESTATE"}
 
 # D3Q19 weights in the library's direction order (for h <-> f conversions)
@@ -61,7 +61,8 @@ EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_inflow_face",
            "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
-           "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read"]
+           "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read",
+           "lbm_halo_pack", "lbm_halo_unpack"]
 
 _lib = None
 
@@ -81,6 +82,8 @@ def load(path: str = LIB_PATH):
         "lbm_destroy": ([P], None),
         "lbm_set_inflow": ([P, I32, P], ctypes.c_int),
         "lbm_set_inflow_face": ([P, I32, P], ctypes.c_int),
+        "lbm_halo_pack": ([P, I32, P], ctypes.c_int),
+        "lbm_halo_unpack": ([P, I32, P], ctypes.c_int),
         "lbm_set_rotation": ([P, P], ctypes.c_int),
         "lbm_set_turbulence": ([P, ctypes.POINTER(_Turbulence)], ctypes.c_int),
         "lbm_turbulence_info": ([P, P, P, P], ctypes.c_int),
@@ -207,6 +210,18 @@ class LBM:
             return
         prof = np.ascontiguousarray(a).reshape(self.nz, 3)
         self._check(self.lib.lbm_set_inflow(self.ctx, int(face), prof.ctypes.data_as(ctypes.c_void_p)))
+
+    def halo_buffer(self):
+        """Device buffer for one side's halo exchange: store [5][nz][nx]."""
+        return torch.empty(5, self.nz, self.nx, dtype=self.store_dtype, device=self.device)
+
+    def halo_pack(self, side, buf):
+        """What this slab sends through side 0 (y-) or 1 (y+) after the last step."""
+        self._check(self.lib.lbm_halo_pack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())))
+
+    def halo_unpack(self, side, buf):
+        """Take what the neighbour on side 0 (y-) or 1 (y+) sent."""
+        self._check(self.lib.lbm_halo_unpack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())))
 
     def set_rotation(self, omega):
         """Rotation vector of the frame in lattice units (x, y, z); zero disables Coriolis."""

@@ -157,6 +157,10 @@ int flux_partial_count();
 // Wave-mask table: pass 0 writes a 0/1 flag per wave into idx (solid
 // neighbour or not); pass 1 fills tab for the waves whose idx >= 0.
 hipError_t launch_wave_masks(const DevCtx& d, int* idx, uint64_t* tab, int pass, hipStream_t s);
+// Halo exchange of a slab along y: pack (unpack = 0) or unpack (1) the five
+// crossing populations of side 0 (y-) or 1 (y+) at the context's phase.
+hipError_t launch_halo(const DevCtx& d, int side, int phase, int unpack, void* buf, hipStream_t s);
+
 hipError_t launch_adjoint(const DevCtx& d, const void* f_t, const void* lam_next, void* lam, const void* probe_src,
                           void* g_inflow, hipStream_t s);
 

@@ -41,6 +41,7 @@ struct lbm_ctx {
     long long n_flux = -1;            // -1: list not built yet
     double* flux_red = nullptr;       // partial sums, then phi at the end
     bool prof_set[6] = {false, false, false, false, false, false};
+    bool halo[6] = {false, false, false, false, false, false};  // LBM_HALO faces (ghost rows)
     double* u0 = nullptr;   // device [nz][3] scratch for initialisation
     int* probes = nullptr;  // device [np][3]
     int np = 0;
@@ -139,6 +140,11 @@ static std::vector<unsigned> block_schedule(const Geo& g, const std::vector<unsi
     std::vector<unsigned> out(b.size());
     for (size_t i = 0; i < b.size(); i++) out[i] = b[i].code;
     return out;
+}
+
+static bool has_halo(const lbm_ctx* c)
+{
+    return c->halo[2] || c->halo[3];
 }
 
 static void free_all(lbm_ctx* c)
@@ -256,7 +262,8 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     if (codec_bytes(params->storage) == 0) return fail(nullptr, LBM_EINVAL, "unknown storage codec");
     for (int a = 0; a < 3; a++) {
         const int lo = params->face[2 * a], hi = params->face[2 * a + 1];
-        if (lo < 0 || lo > 4 || hi < 0 || hi > 4) return fail(nullptr, LBM_EINVAL, "unknown face kind");
+        const int top = a == 1 ? LBM_HALO : 4;   // ghost rows: y faces only
+        if (lo < 0 || lo > top || hi < 0 || hi > top) return fail(nullptr, LBM_EINVAL, "unknown face kind");
         if ((lo == LBM_PERIODIC) != (hi == LBM_PERIODIC)) return fail(nullptr, LBM_EINVAL, "periodic faces must be paired");
     }
     const long long N = (long long)grid->nx * grid->ny * grid->nz;
@@ -291,7 +298,12 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     g.ncx = (g.nx + 63) / 64;
     g.pitch = g.ncx * 64;
     g.wpr = g.ncx;
-    for (int k = 0; k < 6; k++) g.face[k] = params->face[k];
+    // a ghost row is updated like a free-slip face row (its values are
+    // replaced or discarded by the halo exchange)
+    for (int k = 0; k < 6; k++) {
+        c->halo[k] = params->face[k] == LBM_HALO;
+        g.face[k] = c->halo[k] ? F_FREESLIP : params->face[k];
+    }
     g.S = (long long)g.pitch * g.ny * g.nz;
     g.N = N;
     long long goff = 0;
@@ -570,6 +582,7 @@ int lbm_set_rotation(lbm_ctx* c, const double* omega)
 int lbm_set_turbulence(lbm_ctx* c, const lbm_turbulence* p)
 {
     if (!c) return LBM_EINVAL;
+    if (p && has_halo(c)) return fail(c, LBM_ESTATE, "synthetic inflow on a slab (u_ref and e_c span all slabs)");
     VkGen* v = nullptr;
     if (p) {
         std::string err;
@@ -669,6 +682,7 @@ int lbm_net_flux(lbm_ctx* c, double* phi)
 int lbm_balance_flux(lbm_ctx* c, int32_t mode, double* phi_before, double* phi_after)
 {
     if (!c) return LBM_EINVAL;
+    if (mode != 0 && has_halo(c)) return fail(c, LBM_ESTATE, "flux balancing on a slab (the flux spans all slabs)");
     if (mode < 0 || mode > 2) return fail(c, LBM_EINVAL, "flux balancing mode must be 0, 1 or 2");
     int rc = build_flux_cells(c);
     if (rc != LBM_OK) return rc;
@@ -986,6 +1000,7 @@ int lbm_set_stats(lbm_ctx* c, void* acc, int32_t stride)
 int lbm_push_step(lbm_ctx* c, const void* src, void* dst)
 {
     if (!c) return LBM_EINVAL;
+    if (has_halo(c)) return fail(c, LBM_ESTATE, "push step on a slab");
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct device arrays");
     if (c->vk) return fail(c, LBM_ESTATE, "push step with synthetic inflow turbulence on");
     int rc = check_ready(c);
@@ -998,6 +1013,7 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
                      void* g_inflow)
 {
     if (!c) return LBM_EINVAL;
+    if (has_halo(c)) return fail(c, LBM_ESTATE, "adjoint step on a slab");
     if (!f_t || !lam_next || !lam || lam == lam_next) return fail(c, LBM_EINVAL, "bad adjoint arguments");
     {
         // the adjoint kernels address two adjacent adjoint slices with 32-bit byte offsets
@@ -1011,6 +1027,24 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
     HIPCHK(c, launch_adjoint(c->d, f_t, lam_next, lam, probe_src, g_inflow, c->stream), "adjoint step");
+    return LBM_OK;
+}
+
+int lbm_halo_pack(lbm_ctx* c, int32_t side, void* buf)
+{
+    if (!c) return LBM_EINVAL;
+    if (side < 0 || side > 1 || !c->halo[2 + side] || !buf)
+        return fail(c, LBM_EINVAL, "side is not a HALO face, or NULL buffer");
+    HIPCHK(c, launch_halo(c->d, side, c->phase, 0, buf, c->stream), "halo pack");
+    return LBM_OK;
+}
+
+int lbm_halo_unpack(lbm_ctx* c, int32_t side, const void* buf)
+{
+    if (!c) return LBM_EINVAL;
+    if (side < 0 || side > 1 || !c->halo[2 + side] || !buf)
+        return fail(c, LBM_EINVAL, "side is not a HALO face, or NULL buffer");
+    HIPCHK(c, launch_halo(c->d, side, c->phase, 1, const_cast<void*>(buf), c->stream), "halo unpack");
     return LBM_OK;
 }
 
