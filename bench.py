@@ -132,6 +132,50 @@ def adjoint_child(steps):
     return json.loads(r.stdout.strip().splitlines()[-1])["adjoint"]
 
 
+def time_shard(w, n=8, steps=40, warmup=4):
+    """The kilometre grid as n slabs along y (one per rank of an n-GPU run),
+    all on this GPU: every slab steps, then the halo exchange runs (the five
+    crossing populations per interface and direction).  Returns the time per
+    step of all slabs together and of one slab's share, the exchange part,
+    the halo bytes, and whether the slabs match the whole-grid run bit for
+    bit after the timed steps."""
+    import torch
+
+    from paper_2607_04516_amd import binding, slabs
+    whole = binding.from_workload(w)
+    dec = slabs.SlabDecomposition(w, n)
+    s0, _ = whole.get_state()
+    dec.set_state(s0, 0)
+    del s0
+    dec.step(warmup)
+    whole.step(warmup)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    t_step = t_exch = 0.0
+    for _ in range(steps):
+        a, b, c = ev(), ev(), ev()
+        a.record()
+        for lat in dec.slabs:
+            lat.step(1)
+        b.record()
+        dec.exchange()
+        c.record()
+        torch.cuda.synchronize()
+        t_step += a.elapsed_time(b)
+        t_exch += a.elapsed_time(c) - a.elapsed_time(b)
+    whole.step(steps)
+    ref, _ = whole.get_state()
+    same = bool(torch.equal(dec.get_state(), ref))
+    rows = [y1 - y0 for y0, y1 in dec.rows]
+    b = torch.empty(0, dtype=dec.slabs[0].store_dtype).element_size()
+    dec.close()
+    whole.close()
+    per = (t_step + t_exch) / steps
+    return {"slabs": n, "rows_per_slab": rows[0], "ms_per_step_all_slabs": round(per, 4),
+            "ms_per_step_per_slab": round(per / n, 4), "exchange_ms_per_step_all_slabs": round(t_exch / steps, 4),
+            "halo_bytes_per_interface_per_step": 2 * 5 * w.nx * w.nz * b,
+            "bit_identical_to_whole_grid": same}
+
+
 FEATURE_NAMES = ("coriolis", "von_karman_inflow", "sponge", "flux_balance_every_step")
 
 
@@ -237,6 +281,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost run")
     ap.add_argument("--no-features", action="store_true", help="skip the Coriolis / inflow / stabiliser runs")
+    ap.add_argument("--no-shard", action="store_true", help="skip the 8-slab decomposition run")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint-cost workload and print its record (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=1000, help="time steps T of the adjoint workload")
@@ -283,6 +328,12 @@ def main():
         print("[bench] features", file=sys.stderr, flush=True)
         feats = time_features(w, min(args.steps, 100), args.warmup)
         print(f"[bench] features: {feats}", file=sys.stderr, flush=True)
+
+    shard = None
+    if not args.no_shard:
+        print("[bench] 8-slab decomposition", file=sys.stderr, flush=True)
+        shard = time_shard(w, 8, min(args.steps, 40), args.warmup)
+        print(f"[bench] shard: {shard}", file=sys.stderr, flush=True)
 
     copy_gbs = copy_bandwidth()
     print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
@@ -336,6 +387,8 @@ def main():
         line["storage_forms"] = extra
     if feats:
         line["features"] = feats
+    if shard:
+        line["shard"] = shard
     if adj:
         line["adjoint"] = adj
     print(json.dumps(line), flush=True)

@@ -77,3 +77,25 @@ def test_fullsize_sampled_cells(storage, bar):
             worst = max(worst, err)
             assert err <= bar, (x, y, z, err)
     print(f"{storage}: {len(pts)} cells, worst relative error {worst:.2e}", flush=True)
+
+
+def test_fullsize_eight_slabs_bit_identical():
+    """The kilometre grid as eight 800 x 100 x 128 slabs (ghost rows and halo
+    exchange, one per rank of an eight-GPU run) on this GPU matches the
+    whole-grid run bit for bit."""
+    print("case: urban_km 800x800x128 f32 as 8 slabs", flush=True)
+    from paper_2607_04516_amd import slabs
+    w = workloads.urban_km("f32", 12)
+    whole = binding.from_workload(w)
+    dec = slabs.SlabDecomposition(w, 8)
+    s0, _ = whole.get_state()
+    dec.set_state(s0, 0)
+    del s0
+    whole.step(5)
+    dec.step(5)
+    ref, _ = whole.get_state()
+    got = dec.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    dec.close()
+    whole.close()
