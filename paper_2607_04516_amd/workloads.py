@@ -210,3 +210,83 @@ def face_profiles(w: Workload) -> np.ndarray:
     for k, v in w.inflow.items():
         out[k] = v
     return out
+
+
+# --------------------------------------------------------------------------
+# Synthetic building meshes (closed triangle meshes in lattice units) for the
+# voxelizer: the 3D building footprints of the paper's study area are not
+# available, so boxes and rotated prisms stand in.
+# --------------------------------------------------------------------------
+_BOX_FACES = np.array([(0, 2, 1), (0, 3, 2), (4, 5, 6), (4, 6, 7), (0, 1, 5), (0, 5, 4), (1, 2, 6), (1, 6, 5),
+                       (2, 3, 7), (2, 7, 6), (3, 0, 4), (3, 4, 7)])
+
+
+def box_mesh(x0, x1, y0, y1, z0, z1):
+    """[12, 3, 3] triangles of the box [x0, x1] x [y0, y1] x [z0, z1], outward."""
+    v = np.array([[x0, y0, z0], [x1, y0, z0], [x1, y1, z0], [x0, y1, z0],
+                  [x0, y0, z1], [x1, y0, z1], [x1, y1, z1], [x0, y1, z1]], np.float64)
+    return v[_BOX_FACES]
+
+
+def prism_mesh(cx, cy, w, l, angle, z0, z1):
+    """A w x l rectangle centred at (cx, cy), turned by `angle` (radians),
+    extruded from z0 to z1: [12, 3, 3] triangles."""
+    c, s = math.cos(angle), math.sin(angle)
+    pts = []
+    for dx, dy in ((-w / 2, -l / 2), (w / 2, -l / 2), (w / 2, l / 2), (-w / 2, l / 2)):
+        pts.append((cx + c * dx - s * dy, cy + s * dx + c * dy))
+    v = np.array([[p[0], p[1], z0] for p in pts] + [[p[0], p[1], z1] for p in pts], np.float64)
+    return v[_BOX_FACES]
+
+
+def octahedron_mesh(cx, cy, cz, r):
+    """[8, 3, 3] triangles of |x - cx| + |y - cy| + |z - cz| = r."""
+    P = [(cx + r, cy, cz), (cx - r, cy, cz), (cx, cy + r, cz), (cx, cy - r, cz), (cx, cy, cz + r), (cx, cy, cz - r)]
+    faces = [(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)]
+    return np.array([[P[i] for i in f] for f in faces], np.float64)
+
+
+def meshes_to_arrays(meshes):
+    """(triangles [nt, 3, 3], mesh starts [nm + 1]) from a list of meshes."""
+    starts = np.zeros(len(meshes) + 1, np.int32)
+    for i, m in enumerate(meshes):
+        starts[i + 1] = starts[i] + len(m)
+    tris = np.concatenate(meshes).astype(np.float64) if meshes else np.zeros((0, 3, 3))
+    return tris, starts
+
+
+def urban_box_meshes(nx, ny, paf, median, sigma, hmax, seed, footprint=(10, 40), margin_x=32, margin_y=4):
+    """The buildings of urban_heights as box meshes (the same draws), so their
+    voxelization equals heights_to_mask(urban_heights(...))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = np.zeros((ny, nx), np.int32)
+    x_lo, x_hi, y_lo, y_hi = margin_x, nx - margin_x, margin_y, ny - margin_y
+    area = (x_hi - x_lo) * (y_hi - y_lo)
+    region = h[y_lo:y_hi, x_lo:x_hi]
+    meshes = []
+    while np.count_nonzero(region) < paf * area:
+        w = int(rng.integers(footprint[0], footprint[1] + 1))
+        l = int(rng.integers(footprint[0], footprint[1] + 1))
+        x0 = int(rng.integers(x_lo, x_hi))
+        y0 = int(rng.integers(y_lo, y_hi))
+        hb = int(np.clip(round(median * math.exp(sigma * rng.standard_normal())), 1, hmax))
+        xs, xe = x0, min(x0 + w, x_hi)
+        ys, ye = y0, min(y0 + l, y_hi)
+        blk = h[ys:ye, xs:xe]
+        np.maximum(blk, hb, out=blk)
+        meshes.append(box_mesh(xs, xe, ys, ye, 0, hb))
+    return meshes
+
+
+def rotated_building_meshes(nx, ny, count, seed, footprint=(6.0, 30.0), hmax=60.0, margin=8.0):
+    """Rotated rectangular prisms with lognormal heights: general triangles
+    for the voxelizer (no axis-aligned faces)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        w, l = rng.uniform(*footprint, 2)
+        cx = rng.uniform(margin + 20, nx - margin - 20)
+        cy = rng.uniform(margin + 20, ny - margin - 20)
+        hb = float(np.clip(12.0 * math.exp(0.5 * rng.standard_normal()), 2.0, hmax))
+        out.append(prism_mesh(cx, cy, w, l, rng.uniform(0.0, math.pi), 0.0, hb))
+    return out
