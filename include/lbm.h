@@ -300,6 +300,28 @@ int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
                      const void *probe_src, void *g_inflow);
 
+/* Voxelize closed triangle meshes into the solid mask (Sec. 4.1: rays cast
+ * along the grid axes through the cell centres, ray-triangle intersections
+ * and the odd-even parity rule along each ray, independent passes along
+ * other ray directions corroborating the labels; Sec. 2.1: the mask is the
+ * Boolean union of its layers).  tri: host double [nt][3][3], the vertices
+ * (x, y, z) of each triangle in lattice units (cell (x, y, z) is the unit
+ * cube from (x, y, z) to (x + 1, y + 1, z + 1)); starts: host int32 [nm + 1],
+ * mesh m owns triangles starts[m] .. starts[m + 1] - 1 and must be closed.
+ * Each mesh is tested on its own and the meshes are united.  A ray crosses a
+ * triangle where its foot lies in the triangle's projection (counter-
+ * clockwise; a foot on an edge counts only for an edge running upward or
+ * horizontally toward -u, so shared edges count once); a cell centre is
+ * inside a mesh when an odd number of crossings lies below it along the ray.
+ * passes 1: rays along z; 3: rays along z, x and y, solid where at least two
+ * agree.  solid: host uint8 [nz][ny][nx], in/out: voxelized cells are set to
+ * 1, others keep their value.  Synchronous; allocates and frees its device
+ * buffers.  Errors: EINVAL (NULL, counts, starts not running from 0 to nt,
+ * non-finite vertices, passes, a ray longer than 1024 cells), ENOMEM, EHIP;
+ * the message is in lbm_last_error(NULL). */
+int lbm_voxelize(const lbm_grid *grid, const double *tri, int32_t nt, const int32_t *starts, int32_t nm,
+                 int32_t passes, uint8_t *solid);
+
 /* Halo exchange of a slab decomposition along y (one context per slab, the
  * decomposition of the paper's multi-GPU runs).  A slab has a ghost row on
  * each LBM_HALO side (y = 0 for y-, y = ny - 1 for y+) that mirrors the

@@ -62,7 +62,7 @@ EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_inflow_face",
            "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
            "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read",
-           "lbm_halo_pack", "lbm_halo_unpack"]
+           "lbm_halo_pack", "lbm_halo_unpack", "lbm_voxelize"]
 
 _lib = None
 
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
         "lbm_set_inflow": ([P, I32, P], ctypes.c_int),
         "lbm_set_inflow_face": ([P, I32, P], ctypes.c_int),
         "lbm_halo_pack": ([P, I32, P], ctypes.c_int),
+        "lbm_voxelize": ([ctypes.POINTER(_Grid), P, I32, P, I32, I32, P], ctypes.c_int),
         "lbm_halo_unpack": ([P, I32, P], ctypes.c_int),
         "lbm_set_rotation": ([P, P], ctypes.c_int),
         "lbm_set_turbulence": ([P, ctypes.POINTER(_Turbulence)], ctypes.c_int),
@@ -383,6 +384,25 @@ def from_workload(w, storage=None, **kw):
         lat.set_sponge(*w.sponge)
     lat.reset(w.u0)
     return lat
+
+
+def voxelize(shape, tris, starts, passes=1, solid=None):
+    """Solid mask [nz, ny, nx] uint8: `solid` (or zeros) OR the voxelized
+    closed meshes (tris [nt, 3, 3] lattice units, starts [nm + 1]) by the
+    library's ray-parity kernels (lbm_voxelize)."""
+    lib = load()
+    nz, ny, nx = shape
+    out = np.zeros(shape, np.uint8) if solid is None else np.array(solid, np.uint8, copy=True)
+    out = np.ascontiguousarray(out)
+    t = np.ascontiguousarray(tris, np.float64).reshape(-1, 9)
+    s = np.ascontiguousarray(starts, np.int32)
+    g = _Grid(nx, ny, nz)
+    rc = lib.lbm_voxelize(ctypes.byref(g), t.ctypes.data_as(ctypes.c_void_p), int(t.shape[0]),
+                          s.ctypes.data_as(ctypes.c_void_p), int(len(s) - 1), int(passes),
+                          out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise LBMError(rc, lib.lbm_last_error(None).decode())
+    return out
 
 
 OMEGA_EARTH = 7.292115e-5   # rad/s (App. E)

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "lbm.h"
 #include "lbm_device.h"
 
 namespace lbm {
@@ -157,6 +160,11 @@ int flux_partial_count();
 // Wave-mask table: pass 0 writes a 0/1 flag per wave into idx (solid
 // neighbour or not); pass 1 fills tab for the waves whose idx >= 0.
 hipError_t launch_wave_masks(const DevCtx& d, int* idx, uint64_t* tab, int pass, hipStream_t s);
+// Ray-parity voxelizer (lbm_voxel.hip): OR the voxelized meshes into solid
+// (host [nz][ny][nx]); err holds the message on failure.
+int voxelize(const lbm_grid* grid, const double* tri, int32_t nt, const int32_t* starts, int32_t nm, int32_t passes,
+             uint8_t* solid, std::string& err);
+
 // Halo exchange of a slab along y: pack (unpack = 0) or unpack (1) the five
 // crossing populations of side 0 (y-) or 1 (y+) at the context's phase.
 hipError_t launch_halo(const DevCtx& d, int side, int phase, int unpack, void* buf, hipStream_t s);

@@ -1030,6 +1030,15 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
     return LBM_OK;
 }
 
+int lbm_voxelize(const lbm_grid* grid, const double* tri, int32_t nt, const int32_t* starts, int32_t nm,
+                 int32_t passes, uint8_t* solid)
+{
+    std::string err;
+    const int rc = voxelize(grid, tri, nt, starts, nm, passes, solid, err);
+    if (rc != LBM_OK) return fail(nullptr, rc, err);
+    return LBM_OK;
+}
+
 int lbm_halo_pack(lbm_ctx* c, int32_t side, void* buf)
 {
     if (!c) return LBM_EINVAL;
