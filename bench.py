@@ -176,6 +176,25 @@ def time_shard(w, n=8, steps=40, warmup=4):
             "bit_identical_to_whole_grid": same}
 
 
+def time_voxelize(nx=800, ny=800, nz=128):
+    """Voxelize the kilometre workload's buildings (box meshes from the same
+    draws as its height map) with 1 and 3 ray directions; wall time of the
+    call (host input and output included) and whether the mask equals the
+    height-map mask."""
+    from paper_2607_04516_amd import binding, workloads
+    meshes = workloads.urban_box_meshes(nx, ny, 0.30, 12, 0.5, 100, 5, (10, 40), 32, 32)
+    t, s = workloads.meshes_to_arrays(meshes)
+    want = workloads.heights_to_mask(workloads.urban_heights(nx, ny, 0.30, 12, 0.5, 100, 5, (10, 40), 32, 32), nz)
+    out = {"meshes": len(meshes), "triangles": int(len(t)), "cells": nx * ny * nz}
+    for passes in (1, 3):
+        binding.voxelize((nz, ny, nx), t, s, passes)          # warm-up
+        t0 = time.perf_counter()
+        got = binding.voxelize((nz, ny, nx), t, s, passes)
+        out[f"ms_{passes}_pass"] = round((time.perf_counter() - t0) * 1e3, 2)
+        out[f"equals_height_map_{passes}_pass"] = bool((got == want).all())
+    return out
+
+
 FEATURE_NAMES = ("coriolis", "von_karman_inflow", "sponge", "flux_balance_every_step")
 
 
@@ -329,6 +348,10 @@ def main():
         feats = time_features(w, min(args.steps, 100), args.warmup)
         print(f"[bench] features: {feats}", file=sys.stderr, flush=True)
 
+    print("[bench] voxelizer", file=sys.stderr, flush=True)
+    vox = time_voxelize()
+    print(f"[bench] voxelize: {vox}", file=sys.stderr, flush=True)
+
     shard = None
     if not args.no_shard:
         print("[bench] 8-slab decomposition", file=sys.stderr, flush=True)
@@ -389,6 +412,7 @@ def main():
         line["features"] = feats
     if shard:
         line["shard"] = shard
+    line["voxelize"] = vox
     if adj:
         line["adjoint"] = adj
     print(json.dumps(line), flush=True)
