@@ -301,6 +301,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost run")
     ap.add_argument("--no-features", action="store_true", help="skip the Coriolis / inflow / stabiliser runs")
     ap.add_argument("--no-shard", action="store_true", help="skip the 8-slab decomposition run")
+    ap.add_argument("--no-voxelize", action="store_true", help="skip the voxelizer run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 2 GiB device buffer three times: the known-size kernel that scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint-cost workload and print its record (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=1000, help="time steps T of the adjoint workload")
@@ -319,6 +323,16 @@ def main():
     from paper_2607_04516_amd import binding, workloads
     binding.load()
     torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        a = torch.ones(512 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
 
     if args.adjoint_only:
         print("[bench] adjoint workload", file=sys.stderr, flush=True)
@@ -348,9 +362,11 @@ def main():
         feats = time_features(w, min(args.steps, 100), args.warmup)
         print(f"[bench] features: {feats}", file=sys.stderr, flush=True)
 
-    print("[bench] voxelizer", file=sys.stderr, flush=True)
-    vox = time_voxelize()
-    print(f"[bench] voxelize: {vox}", file=sys.stderr, flush=True)
+    vox = None
+    if not args.no_voxelize:
+        print("[bench] voxelizer", file=sys.stderr, flush=True)
+        vox = time_voxelize()
+        print(f"[bench] voxelize: {vox}", file=sys.stderr, flush=True)
 
     shard = None
     if not args.no_shard:
@@ -412,7 +428,8 @@ def main():
         line["features"] = feats
     if shard:
         line["shard"] = shard
-    line["voxelize"] = vox
+    if vox:
+        line["voxelize"] = vox
     if adj:
         line["adjoint"] = adj
     print(json.dumps(line), flush=True)
