@@ -58,7 +58,7 @@ class InflowProblem:
         ckpts = []
         for _ in range(self.T // self.K):
             if keep_checkpoints:
-                ckpts.append(lat.get_state()[0].clone())
+                ckpts.append(lat.get_state()[0])          # a fresh tensor per checkpoint
             lat.step_probed(self.K, acc)
         self.forward_calls += 1
         return acc.double() / self.T, ckpts
@@ -71,10 +71,10 @@ class InflowProblem:
         lam_next = torch.zeros(19, lat.nz, lat.ny, lat.nx, dtype=self.rdt, device=self.device)
         lam = torch.empty_like(lam_next)
         g = torch.zeros(2, 6, lat.nz, 3, dtype=self.rdt, device=self.device)
-        snaps = [lat.new_state() for _ in range(K + 1)]
+        work = [lat.new_state() for _ in range(K)]
         for seg in range(T // K - 1, -1, -1):
             t0 = seg * K
-            snaps[0].copy_(ckpts[seg])
+            snaps = [ckpts[seg]] + work          # the checkpoint is only read
             for k in range(K):
                 lat.push_step(snaps[k], snaps[k + 1])
             last = t0 + K

@@ -318,6 +318,21 @@ __device__ inline void adjoint_cell(const typename Codec<K>::store* __restrict__
 // solid or beyond a WALL face (halfway bounce-back transposed).  One wave is one
 // 64-cell chunk of a row; the slot of each direction is one shared lane
 // offset plus a wave-uniform base, selected per lane by the solid lane mask.
+//
+// With an INFLOW x- face and an OUTFLOW x+ face (adj_x_edges) the waves also
+// take the four x-face layers of their rows, with per-lane masks instead of
+// the general path (whose scattered reads of these columns would fetch
+// lines the row's waves fetch as well):
+//   x = 0       an inflow cell: lam = 0;
+//   x = 1       the populations moving toward x = 0 land in the inflow cell
+//               and are dropped, unless that cell is solid (bounce-back);
+//   x = nx - 2  a population bounced back toward x+ also fills the outflow
+//               copy of its slot in the face cell x = nx - 1, when fluid;
+//   x = nx - 1  a population leaving through the outflow face is dropped
+//               unless the cell at nx - 2 is solid (then it is its own
+//               bounce-back slot), and one moving to nx - 2 also fills the
+//               outflow copy of that slot in the face cell of its row.
+
 template <int K>
 __device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__ f_t,
                                     const typename Codec<K>::real* __restrict__ lam_next,
@@ -342,14 +357,82 @@ __device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__
     uint64_t any = 0;
     adj_static_for<1, NQ>([&](auto ic) { any |= solid_src_mask<decltype(ic)::value>(W); });
     const bool solid_any = uniform_u64(any) != 0;
-    if (x < B.x0 || x > B.x1) return;
+    const bool xe = adj_x_edges(g);
+    if (x >= g.nx || (!xe && (x < B.x0 || x > B.x1))) return;
     const long long cell = (long long)x + (long long)g.nx * row;
     const uint32_t off = (uint32_t)cell * (uint32_t)sizeof(R);
     const char* lbase = (const char*)lam_next;
-    // a solid lane stores 0 with the same store instructions as the rest
-    const bool solid_lane = (own >> lane) & 1ull;
+    // lane masks of the x-face layers in this chunk (wave-uniform)
+    const int base = cx * 64;
+    const uint64_t e0 = (xe && base == 0) ? 1ull : 0ull;
+    const uint64_t e1 = (xe && base == 0) ? 2ull : 0ull;
+    const int lb = g.nx - 2 - base, la = g.nx - 1 - base;
+    const uint64_t eb = (xe && lb >= 0 && lb < 64) ? 1ull << lb : 0ull;
+    const uint64_t ea = (xe && la >= 0 && la < 64) ? 1ull << la : 0ull;
+    // a solid lane (and the inflow cell x = 0) stores 0 with the same store
+    // instructions as the rest
+    const bool solid_lane = ((own | e0) >> lane) & 1ull;
     R ls[NQ], h[NQ];
-    if (!solid_any) {
+    if ((e0 | e1 | eb | ea) != 0) {
+        const uint64_t xm_solid = solid_src_mask<1>(W);   // cell x - 1 of the row is solid
+        const uint64_t xp_solid = solid_src_mask<2>(W);   // cell x + 1 of the row is solid
+        // every slot first, without branches, so that the loads issue together;
+        // lanes whose value is their own slot or nothing read the own slot
+        uint32_t so[NQ];
+        adj_static_for<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (I == 0) {
+                so[0] = off;
+                ls[0] = *(const R*)(lbase + off);
+            } else {
+                constexpr V3 c = dirv(I);
+                uint64_t force = e0;
+                if constexpr (c.x == 1) force |= e1;
+                if constexpr (c.x == -1) force |= ea;
+                so[I] = lane_select(off + O.on[I], off + O.oo[I], solid_src_mask<I>(W) | force);
+                ls[opp(I)] = *(const R*)(lbase + O.lo[I] + so[I]);
+            }
+        });
+        // the outflow copies: the slot at nx - 2 of a population moving to
+        // nx - 2 from the face cell, and its copy one cell further in x
+        if (ea != 0) {
+            R pv[NQ];
+            adj_static_for<1, NQ>([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                constexpr V3 c = dirv(I);
+                if constexpr (c.x == 1) {
+                    const uint64_t part = ea & ~solid_src_mask<I>(W) & ~W.c[1 - c.z][1 - c.y];
+                    pv[I] = *(const R*)(lbase + O.lo[I] + lane_select(so[I], so[I] + (uint32_t)sizeof(R), part));
+                }
+            });
+            adj_static_for<1, NQ>([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                constexpr V3 c = dirv(I);
+                if constexpr (c.x == 1) {
+                    const uint64_t part = ea & ~solid_src_mask<I>(W) & ~W.c[1 - c.z][1 - c.y];
+                    if ((part >> lane) & 1ull) ls[opp(I)] += pv[I];
+                }
+            });
+        }
+        adj_static_for<1, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            const uint64_t sm = solid_src_mask<I>(W);
+            if constexpr (c.x == 1) {
+                if (((e1 & ~sm) >> lane) & 1ull) ls[opp(I)] = R(0);
+            }
+            if constexpr (c.x == -1) {
+                if (((ea & ~xm_solid) >> lane) & 1ull) ls[opp(I)] = R(0);
+                // the own slot of a bounce-back at nx - 2 and its copy (rare:
+                // a solid next to the outflow face)
+                const uint64_t part = eb & sm & ~xp_solid;
+                if (uniform_u64(part) != 0) {
+                    const R q = *(const R*)(lbase + O.lo[I] + lane_select(so[I], so[I] + (uint32_t)sizeof(R), part));
+                    if ((part >> lane) & 1ull) ls[opp(I)] += q;
+                }
+            }
+        });
+    } else if (!solid_any) {
         adj_static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             ls[opp(I)] = *(const R*)(lbase + O.odd[I] + off);

@@ -718,6 +718,14 @@ __host__ __device__ inline int face_layers(int kind, int adjoint)
     return 1;
 }
 
+// Whether the adjoint's wave blocks take the x-face layers of their rows
+// too (an INFLOW x- face and an OUTFLOW x+ face; per-lane rules in the
+// adjoint kernel).
+__host__ __device__ inline bool adj_x_edges(const Geo& g)
+{
+    return g.face[0] == F_INFLOW && g.face[1] == F_OUTFLOW && g.nx >= 4;
+}
+
 // Row class of the fast kernels: 3 cy + cz with cy = 1 (2) for the y = 0
 // (y = ny - 1) row of a FREESLIP face, else 0, and cz likewise for z.  In
 // such a row every direction that crosses the face pulls the mirrored

@@ -395,7 +395,10 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
                 const unsigned n = (unsigned)(x + (long long)g.nx * (y + (long long)g.ny * z));
                 const Box bp = main_box(g, 0), ba = main_box(g, 1);
                 if (x < bp.x0 || x > bp.x1 || y < bp.y0 || y > bp.y1 || z < bp.z0 || z > bp.z1) plist.push_back(n);
-                if (x < ba.x0 || x > ba.x1 || y < ba.y0 || y > ba.y1 || z < ba.z0 || z > ba.z1) alist.push_back(n);
+                // with an inflow x- face and an outflow x+ face the adjoint's
+                // waves take their rows' x-face layers as well
+                const bool xin = adj_x_edges(g) || (x >= ba.x0 && x <= ba.x1);
+                if (!xin || y < ba.y0 || y > ba.y1 || z < ba.z0 || z > ba.z1) alist.push_back(n);
             }
     if ((rc = device_alloc(c, (void**)&c->push_list, plist.size() * sizeof(unsigned), "cell list")) != LBM_OK ||
         (rc = device_alloc(c, (void**)&c->adj_list, alist.size() * sizeof(unsigned), "cell list")) != LBM_OK) {

@@ -89,6 +89,42 @@ def test_adjoint_step_freeslip_rows_multichunk_f64():
     assert np.abs(g_g - g_o).max() <= 1e-12 * np.abs(g_o).max()
 
 
+X_EDGE_FACES = [
+    ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip"),
+    ("inflow", "outflow", "inflow", "outflow", "wall", "freeslip"),
+    ("inflow", "outflow", "periodic", "periodic", "freeslip", "outflow"),
+]
+
+
+@pytest.mark.parametrize("fi", range(len(X_EDGE_FACES)))
+@pytest.mark.parametrize("dims", [(5, 6, 5), (65, 5, 4), (66, 5, 4), (130, 4, 5)])
+def test_adjoint_step_x_face_lanes_f64(fi, dims):
+    """The x-face layers of an inflow/outflow pair inside the adjoint's waves:
+    solids in and next to both face columns (bounce-back into and out of the
+    outflow copies, solid inflow cells), face columns on either side of a
+    64-cell chunk boundary."""
+    print(f"case: adjoint x-face lanes faces {X_EDGE_FACES[fi]} dims {dims}", flush=True)
+    nx, ny, nz = dims
+    rng = np.random.default_rng(31 + fi + nx)
+    solid = (rng.random((nz, ny, nx)) < 0.08).astype(np.uint8)
+    for cols in ((0, 1, 2), (nx - 3, nx - 2, nx - 1)):
+        for x in cols:
+            solid[:, :, x] |= (rng.random((nz, ny)) < 0.3).astype(np.uint8)
+    w = small_workload(nx, ny, nz, X_EDGE_FACES[fi], solid=solid, tau0=0.53, c_smag=0.15,
+                       u=(0.05, 0.02, 0.01), noise=5e-3, seed=fi + 40)
+    o = oracle_for(w)
+    f = o.run(oracle_init(o, w), 3)
+    m = fluid_mask(w)
+    lam_next = rng.standard_normal(f.shape) * m[None]
+    probes = np.argwhere(m)[:: max(1, m.sum() // 5)][:5][:, ::-1].astype(np.int32)
+    src = rng.standard_normal((len(probes), 3))
+    lam_o, g_o = o.adjoint_step(f, lam_next, probes, src)
+    lam_g, g_g = _gpu_adjoint(w, f, lam_next, probes, src)
+    err = np.abs(lam_g - lam_o)
+    assert err.max() <= 1e-12 * np.abs(lam_o).max(), np.argwhere(err > 1e-12 * np.abs(lam_o).max())[:6].tolist()
+    assert np.abs(g_g - g_o).max() <= 1e-12 * max(np.abs(g_o).max(), 1e-30)
+
+
 def test_adjoint_step_force_f64():
     w, o, f, lam_next, probes, src = _problem(0, (9, 6, 5), "f64", force=(2e-5, -1e-5, 3e-6))
     lam_o, g_o = o.adjoint_step(f, lam_next, probes, src)
