@@ -726,6 +726,16 @@ __host__ __device__ inline bool adj_x_edges(const Geo& g)
     return g.face[0] == F_INFLOW && g.face[1] == F_OUTFLOW && g.nx >= 4;
 }
 
+// Whether the push kernel's wave blocks take the x-face cells of row (y, z)
+// too: an INFLOW x- face and an OUTFLOW x+ face, 32-bit or wider storage,
+// and a row not next to an INFLOW y or z face.
+__host__ __device__ inline bool push_x_edge_row(const Geo& g, int wide, int y, int z)
+{
+    return wide && g.face[0] == F_INFLOW && g.face[1] == F_OUTFLOW && g.nx >= 4 &&
+           !(g.face[2] == F_INFLOW && y == 1) && !(g.face[3] == F_INFLOW && y == g.ny - 2) &&
+           !(g.face[4] == F_INFLOW && z == 1) && !(g.face[5] == F_INFLOW && z == g.nz - 2);
+}
+
 // Row class of the fast kernels: 3 cy + cz with cy = 1 (2) for the y = 0
 // (y = ny - 1) row of a FREESLIP face, else 0, and cz likewise for z.  In
 // such a row every direction that crosses the face pulls the mirrored

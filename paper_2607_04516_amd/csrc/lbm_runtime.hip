@@ -394,7 +394,9 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
             for (int x = 0; x < g.nx; x++) {
                 const unsigned n = (unsigned)(x + (long long)g.nx * (y + (long long)g.ny * z));
                 const Box bp = main_box(g, 0), ba = main_box(g, 1);
-                if (x < bp.x0 || x > bp.x1 || y < bp.y0 || y > bp.y1 || z < bp.z0 || z > bp.z1) plist.push_back(n);
+                // the push's waves take the x-face cells of some rows as well
+                const bool pin = (x >= bp.x0 && x <= bp.x1) || push_x_edge_row(g, params->storage <= LBM_F32, y, z);
+                if (!pin || y < bp.y0 || y > bp.y1 || z < bp.z0 || z > bp.z1) plist.push_back(n);
                 // with an inflow x- face and an outflow x+ face the adjoint's
                 // waves take their rows' x-face layers as well
                 const bool xin = adj_x_edges(g) || (x >= ba.x0 && x <= ba.x1);

@@ -359,10 +359,18 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
         if constexpr (ROWS) return solid_src_mask<I>(W);
         else return WM.template get<I>();
     };
-    if (x < B.x0 || x > B.x1) return;
+    // rows whose x-face cells this wave takes as well (inflow x-, outflow x+)
+    const bool xr = push_x_edge_row(g, ROWS, y, z);
+    if (x >= g.nx || (!xr && (x < B.x0 || x > B.x1))) return;
     const uint32_t off = (uint32_t)((long long)x + (long long)g.nx * row) * (uint32_t)sizeof(T);
     const char* sbase = (const char*)src;
     char* dbase = (char*)dst;
+    // lane masks (wave-uniform): the inflow cell x = 0, its neighbour x = 1,
+    // the outflow face cell x = nx - 1
+    const uint64_t e0 = (xr && cx == 0) ? 1ull : 0ull;
+    const uint64_t e1 = (xr && cx == 0) ? 2ull : 0ull;
+    const int la = g.nx - 1 - cx * 64;
+    const uint64_t ea = (xr && la >= 0 && la < 64) ? 1ull << la : 0ull;
     // A solid lane writes 0 into its own 19 slots with the same store
     // instructions as the fluid lanes (no fluid lane pushes into a solid
     // cell, so the addresses never collide).
@@ -378,6 +386,49 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
     }
     R drho, ux, uy, uz, tau;
     collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
+    if ((e0 | e1 | ea) != 0) {
+        // x-face cells of the row.  The inflow cell x = 0 outputs its own
+        // equilibrium in its own slots and pushes it toward x = 1; the
+        // populations of x = 1 moving to x = 0 are dropped (unless x = 0 is
+        // solid: bounce-back); those of the outflow face cell leaving through
+        // the face are dropped unless the cell at nx - 2 is solid (then they
+        // are its bounce-back).  The outflow copies follow in their own
+        // launch, as for the face-shell cells.
+        if (e0 != 0 && !solid_lane && lane == 0) {
+            R vx, vy, vz, heq[NQ];
+            load_inflow<R>(uin, g, 0, 0, y, z, vx, vy, vz);
+            equilibrium_shifted<R>(P.rho0, R(0), vx, vy, vz, heq);
+#pragma unroll
+            for (int i = 0; i < NQ; i++) h[i] = heq[i] * R(C::SC);
+        }
+        const uint64_t xm_solid = smask(std::integral_constant<int, 1>{});   // cell x - 1 of the row is solid
+        const bool inflow_lane = ((e0 >> lane) & 1ull) != 0;
+        sfor<0, NQ>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr V3 c = dirv(I);
+            if constexpr (I == 0) {
+                st_pop((T*)(dbase + off), C::pack(solid_lane ? R(0) : h[0]));
+            } else {
+                const uint64_t sm = smask(ic);
+                uint64_t force = own | e0;
+                uint64_t skip = 0;
+                if constexpr (c.x == 1) skip = e1 & ~sm & ~own;
+                if constexpr (c.x == -1) {
+                    force |= ea;
+                    skip = ea & ~xm_solid & ~own;
+                }
+                const uint32_t so = lane_select(off + O.on[I], off + O.oo[I], sm | force);
+                const R v = solid_lane ? R(0) : (inflow_lane ? h[I] : h[opp(I)]);
+                if (!((skip >> lane) & 1ull)) st_pop((T*)(dbase + O.lo[I] + so), C::pack(v));
+                if constexpr (c.x == -1) {
+                    // off + on wraps modulo 2^32 like the other slot offsets
+                    const uint32_t sn = off + O.on[I];
+                    if (inflow_lane && !solid_lane && !(sm & 1ull)) st_pop((T*)(dbase + O.lo[I] + sn), C::pack(h[opp(I)]));
+                }
+            }
+        });
+        return;
+    }
     // INFLOW face layers next to this wave (wave-uniform): the x- layer
     // when the chunk holds x = 1, the x+ layer when it holds x = nx - 2, the
     // y and z layers when the row is next to them.  Only a direction whose
