@@ -526,7 +526,8 @@ __device__ inline void adjoint_inflow(const typename Codec<K>::real* __restrict_
 // One adjoint step in one launch, blocks in the order of the context's
 // block schedule: per-cell blocks take the listed face-shell cells on the
 // general path, inflow blocks the inflow gradient (one per INFLOW face and
-// height; none without g), wave blocks the waves of main_box(g, 1).  All of
+// height; none without g), wave blocks the waves of main_box(g, 1) (whole
+// rows of it when adj_x_edges holds).  All of
 // them only read f_t and lam_next and write disjoint parts of lam and g, so
 // the latency-bound per-cell and inflow blocks run alongside the interior,
 // each next to the wave blocks of its rows.

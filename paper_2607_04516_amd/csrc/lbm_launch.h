@@ -35,9 +35,9 @@ struct DevCtx {
     const double* uin;    // per-cell inflow velocities (inflow_slot); what the step kernels read
     const unsigned* odd_list;  // waves of the odd step left to the general kernel
     long long odd_list_n;
-    const unsigned* push_list; // canonical indices of the face layer (general-path push)
+    const unsigned* push_list; // canonical indices of the face-layer cells the push's waves do not take
     long long push_list_n;
-    const unsigned* adj_list;  // canonical indices of the two-layer face shell (general-path adjoint)
+    const unsigned* adj_list;  // canonical indices of the face-shell cells the adjoint's waves do not take
     long long adj_list_n;
     const unsigned* push_sched;  // block order of the push launch (kind << 30 | index)
     unsigned push_sched_n;

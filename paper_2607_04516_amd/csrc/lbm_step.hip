@@ -267,7 +267,8 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
 // schedule.  Per-cell blocks run the general per-cell code for the face
 // layer outside main_box(g, 0) (the listed cells); inflow cells among them
 // write their canonical equilibrium into their own slots.  Wave blocks take
-// the waves of main_box(g, 0):
+// the waves of main_box(g, 0), and with an inflow x- and an outflow x+ face
+// also the x-face cells of the rows push_x_edge_row names:
 // local read, collision, push of f*_opp(I) into the slot the pull of I
 // resolves to (own slot at solid neighbours and across WALL faces).  Waves
 // next to an INFLOW face skip the pushes that land in an inflow cell, so
