@@ -215,7 +215,7 @@ def test_push_step_x_face_cells(fi, dims):
     solid = (rng.random((nz, ny, nx)) < 0.08).astype(np.uint8)
     for x in (0, 1, 2, nx - 3, nx - 2, nx - 1):
         solid[:, :, x] |= (rng.random((nz, ny)) < 0.3).astype(np.uint8)
-    for storage in ("f64", "f32"):
+    for storage in ("f64", "f32", "f16s"):
         w = small_workload(nx, ny, nz, X_EDGE_FACES[fi], solid=solid, tau0=0.53, c_smag=0.15,
                            u=(0.05, 0.02, 0.01), noise=5e-3, seed=fi + 60, storage=storage)
         lat = binding.from_workload(w)
@@ -241,3 +241,30 @@ def test_push_step_x_face_cells(fi, dims):
                 torch.cuda.synchronize()
                 assert torch.equal(a, ref), step
         lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+@pytest.mark.parametrize("fi", [0, 1])
+def test_adjoint_step_16bit_snapshots(storage, fi):
+    """The adjoint with 16-bit stored states (FP32 arithmetic): against the
+    oracle adjoint at the same decoded state, to the FP32 bar."""
+    print(f"case: adjoint {storage} faces {X_EDGE_FACES[fi]}", flush=True)
+    nx, ny, nz = 66, 6, 5
+    rng = np.random.default_rng(71 + fi)
+    solid = (rng.random((nz, ny, nx)) < 0.08).astype(np.uint8)
+    w = small_workload(nx, ny, nz, X_EDGE_FACES[fi], solid=solid, tau0=0.53, c_smag=0.15,
+                       u=(0.05, 0.02, 0.01), noise=5e-3, seed=fi + 80, storage=storage)
+    o = oracle_for(w)
+    lat = binding.from_workload(w)
+    f = lat.state_to_f64(lat.f64_to_state(o.run(oracle_init(o, w), 3)))   # the state the GPU sees
+    lat.close()
+    m = fluid_mask(w)
+    lam_next = rng.standard_normal(f.shape) * m[None]
+    probes = np.argwhere(m)[:: max(1, m.sum() // 5)][:5][:, ::-1].astype(np.int32)
+    src = rng.standard_normal((len(probes), 3))
+    lam_o, g_o = o.adjoint_step(f, lam_next, probes, src)
+    lam_g, g_g = _gpu_adjoint(w, f, lam_next, probes, src)
+    err = np.abs(lam_g - lam_o).max() / np.abs(lam_o).max()
+    gerr = np.abs(g_g - g_o).max() / np.abs(g_o).max()
+    print(f"{storage} adjoint relative errors: lam {err:.2e}, g {gerr:.2e}", flush=True)
+    assert err <= 2e-5 and gerr <= 2e-5
