@@ -339,6 +339,9 @@ def main():
         print(json.dumps({"adjoint": time_adjoint(args.adjoint_steps)}), flush=True)
         return
 
+    # the copy ceiling first, on a fresh device heap
+    copy_gbs = copy_bandwidth()
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     print(f"[bench] building workload {args.nx}x{args.ny}x{args.nz}", file=sys.stderr, flush=True)
     w = workloads.urban_km("f32", nx=args.nx, ny=args.ny, nz=args.nz)
     res = time_forward(w, args.storage, args.steps, args.warmup)
@@ -374,8 +377,6 @@ def main():
         shard = time_shard(w, 8, min(args.steps, 40), args.warmup)
         print(f"[bench] shard: {shard}", file=sys.stderr, flush=True)
 
-    copy_gbs = copy_bandwidth()
-    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     traffic, _ = traffic_from_profiles(args.storage)
 
     adj = None
