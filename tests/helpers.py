@@ -45,3 +45,39 @@ def fluid_mask(w):
         idx[2 - a] = n - 1 if side else 0
         m[tuple(idx)] = False
     return m
+
+
+# Face sets of the boundary matrix: every face kind on every axis, corners
+# between inflow and outflow faces, two inflow faces, periodic wraps.
+FACE_SETS = [
+    ("periodic",) * 6,
+    ("wall", "wall", "freeslip", "freeslip", "wall", "freeslip"),
+    ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip"),
+    ("inflow", "outflow", "inflow", "outflow", "wall", "freeslip"),
+    ("outflow", "inflow", "outflow", "outflow", "freeslip", "outflow"),
+    ("periodic", "periodic", "wall", "wall", "inflow", "outflow"),
+    ("freeslip", "freeslip", "periodic", "periodic", "freeslip", "freeslip"),
+    ("outflow", "outflow", "outflow", "outflow", "outflow", "outflow"),
+]
+
+
+def window_index(pts, faces, nx, ny, nz):
+    """Index arrays (zi, yi, xi), broadcastable to [n, 5, 5, 5], of the 5x5x5
+    windows centred on the cells pts [n, 3] (x, y, z): coordinates wrap on
+    an axis whose faces are periodic and are clamped otherwise (a pull never
+    reaches past a non-periodic face, so clamped entries are never read)."""
+    pts = np.asarray(pts, np.int64)
+    d = np.arange(-2, 3)
+    out = []
+    for a, n in enumerate((nx, ny, nz)):
+        v = pts[:, a, None] + d
+        periodic = faces[2 * a] in ("periodic", oracle.PERIODIC)
+        out.append(np.mod(v, n) if periodic else np.clip(v, 0, n - 1))
+    xi, yi, zi = out
+    return zi[:, :, None, None], yi[:, None, :, None], xi[:, None, None, :]
+
+
+def windows_np(f, pts, faces, nx, ny, nz):
+    """Windows [n, 19, 5, 5, 5] of a state f [19, nz, ny, nx]."""
+    zi, yi, xi = window_index(pts, faces, nx, ny, nz)
+    return np.ascontiguousarray(np.moveaxis(f[:, zi, yi, xi], 0, 1))

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import oracle_for
+from helpers import oracle_for, window_index
 from paper_2607_04516_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -39,29 +39,28 @@ def _samples(w, rng, n_random=1500):
     return np.array(pts, np.int64)
 
 
-def _windows(state, pts, nx, ny, nz):
-    d = torch.arange(-2, 3, device=state.device)
-    P = torch.from_numpy(pts).to(state.device)
-    xi = (P[:, 0, None] + d).clamp(0, nx - 1)[:, None, None, :]
-    yi = (P[:, 1, None] + d).clamp(0, ny - 1)[:, None, :, None]
-    zi = (P[:, 2, None] + d).clamp(0, nz - 1)[:, :, None, None]
+def _windows(state, pts, faces, nx, ny, nz):
+    zi, yi, xi = (torch.from_numpy(a).to(state.device) for a in window_index(pts, faces, nx, ny, nz))
     win = state[:, zi, yi, xi]            # [19, S, 5, 5, 5]
     return win.permute(1, 0, 2, 3, 4).contiguous()
 
 
+@pytest.mark.parametrize("t0", [10, 11])
 @pytest.mark.parametrize("storage,bar", [("f64", 1e-12), ("f32", 1e-6), ("f16s", None)])
-def test_fullsize_sampled_cells(storage, bar):
-    print(f"case: urban_km 800x800x128 {storage}, sampled one-step parity", flush=True)
+def test_fullsize_sampled_cells(storage, bar, t0):
+    """From an even time the next launch is the even (local) kernel, from an
+    odd time the odd (gather) kernel."""
+    print(f"case: urban_km 800x800x128 {storage}, sampled one-step parity from t = {t0}", flush=True)
     w = workloads.urban_km(storage, 12)
     lat = binding.from_workload(w)
-    lat.step(11)                           # odd time: the state sits in the swapped layout
+    lat.step(t0)
     ft, t = lat.get_state()
     ft = ft.clone()
     lat.step(1)
     fn, _ = lat.get_state()
     torch.cuda.synchronize()
     pts = _samples(w, np.random.default_rng(1))
-    win = _windows(ft, pts, w.nx, w.ny, w.nz).to(torch.float64).cpu().numpy() / lat.scale
+    win = _windows(ft, pts, w.faces, w.nx, w.ny, w.nz).to(torch.float64).cpu().numpy() / lat.scale
     win += W_[None, :, None, None, None]
     got = fn[:, pts[:, 2], pts[:, 1], pts[:, 0]].to(torch.float64).cpu().numpy().T / lat.scale + W_
     o = oracle_for(w)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import fluid_mask, oracle_for, oracle_init, small_workload
+from helpers import FACE_SETS, fluid_mask, oracle_for, oracle_init, small_workload
 from paper_2607_04516_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -70,16 +70,6 @@ def test_cube_reduced_precision_velocity(storage, bar):
 
 
 # --------------------------------------------------------------------------- boundary matrix
-FACE_SETS = [
-    ("periodic",) * 6,
-    ("wall", "wall", "freeslip", "freeslip", "wall", "freeslip"),
-    ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip"),
-    ("inflow", "outflow", "inflow", "outflow", "wall", "freeslip"),
-    ("outflow", "inflow", "outflow", "outflow", "freeslip", "outflow"),
-    ("periodic", "periodic", "wall", "wall", "inflow", "outflow"),
-    ("freeslip", "freeslip", "periodic", "periodic", "freeslip", "freeslip"),
-    ("outflow", "outflow", "outflow", "outflow", "outflow", "outflow"),
-]
 
 
 def _solid_small(nx, ny, nz, seed):
