@@ -232,7 +232,10 @@ int lbm_reset(lbm_ctx *ctx, const double *u0);
 int lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* As lbm_step, and after every step adds u(x_p, t+1) of each registered
- * probe cell (lbm_set_probes) to acc: device real [np][3]. */
+ * probe cell (lbm_set_probes) to acc: device real [2][np][3], a
+ * Neumaier-compensated sum: acc[0] the running sum, acc[1] the accumulated
+ * rounding errors; the accumulated value is acc[0] + acc[1].  The caller
+ * zeroes acc before the first call of a sum. */
 int lbm_step_probed(lbm_ctx *ctx, int64_t n, void *acc);
 
 /* Macroscopic fields of the current state (eq. D.1; nu_t from eqs. D.6, D.11
@@ -259,7 +262,10 @@ int lbm_mass(lbm_ctx *ctx, double *mass, double *kinetic_energy);
 int lbm_get_state(lbm_ctx *ctx, void *dst, int64_t *t);
 
 /* Import a canonical state (device store [19][N]) as time t.  Values of
- * solid and inflow cells are ignored. */
+ * solid and inflow cells are ignored.  With the watchdog on
+ * (watchdog_stride > 0) the imported state is checked at once (synchronises):
+ * EUNSTABLE for a non-finite value, |u| > 0.5 or |rho - rho0| > 0.5 in a
+ * fluid cell (a corrupt checkpoint); the state stays imported. */
 int lbm_set_state(lbm_ctx *ctx, const void *src, int64_t t);
 
 /* Register integer probe cells: host int32 [np][3] = (x, y, z), each a
@@ -267,8 +273,8 @@ int lbm_set_state(lbm_ctx *ctx, const void *src, int64_t t);
  * lbm_probe_accumulate and lbm_adjoint_step. */
 int lbm_set_probes(lbm_ctx *ctx, const int32_t *cells, int32_t np);
 
-/* acc (device real [np][3]) += u of the registered probe cells in the
- * current state. */
+/* acc (device real [2][np][3], compensated as in lbm_step_probed) += u of
+ * the registered probe cells in the current state. */
 int lbm_probe_accumulate(lbm_ctx *ctx, void *acc);
 
 /* Time statistics: while set, every step from a time t with t % stride == 0

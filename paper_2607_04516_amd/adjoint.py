@@ -54,14 +54,14 @@ class InflowProblem:
         lat = self.lat
         lat.set_inflow(self.face, self.profile(speeds, theta))
         lat.reset(self.u0)
-        acc = torch.zeros(self.probes.shape[0], 3, dtype=self.rdt, device=self.device)
+        acc = torch.zeros(2, self.probes.shape[0], 3, dtype=self.rdt, device=self.device)   # sum, compensation
         ckpts = []
         for _ in range(self.T // self.K):
             if keep_checkpoints:
                 ckpts.append(lat.get_state()[0])          # a fresh tensor per checkpoint
             lat.step_probed(self.K, acc)
         self.forward_calls += 1
-        return acc.double() / self.T, ckpts
+        return (acc[0].double() + acc[1].double()) / self.T, ckpts
 
     def run_backward(self, ckpts, g_ubar: torch.Tensor, speeds, theta):
         """Returns (d/d speeds [nz], d/d theta) as float64 numpy values."""

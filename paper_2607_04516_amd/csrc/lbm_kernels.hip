@@ -395,9 +395,16 @@ __global__ void k_probe_cells(const typename Codec<K>::store* f, const uint64_t*
     if (p >= np) return;
     R v[4];
     cell_rho_u<K>(f, mask, uin, g, L, P, phase, cells[3 * p], cells[3 * p + 1], cells[3 * p + 2], v);
-    acc[3 * p] += v[1];
-    acc[3 * p + 1] += v[2];
-    acc[3 * p + 2] += v[3];
+    // Neumaier summation: acc[0][p] holds the running sum, acc[1][p] the
+    // accumulated rounding errors of its additions
+    R* sum = acc + 3 * p;
+    R* cmp = acc + 3 * (long long)np + 3 * p;
+    for (int a = 0; a < 3; a++) {
+        const R s = sum[a], x = v[1 + a];
+        const R t = s + x;
+        cmp[a] += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+        sum[a] = t;
+    }
 }
 
 // --------------------------------------------------------------------------

@@ -922,6 +922,9 @@ int lbm_set_state(lbm_ctx* c, const void* src, int64_t t)
     HIPCHK(c, launch_import(c->d, src, c->stream), "import kernel");
     c->phase = 0;
     c->t = t;
+    // with the watchdog on, a corrupt state (non-finite or out-of-range
+    // values) is reported at once instead of at the next check
+    if (c->p.watchdog_stride > 0) return watchdog(c);
     return LBM_OK;
 }
 

@@ -1,0 +1,237 @@
+"""Diagnostics at reduced precision and the watchdog (needs an MI355X).
+
+The macros (rho, u, nu_t), the mass and kinetic energy, point probes, the
+compensated probe accumulator and the time statistics of FP32, shifted
+binary16 and bfloat16 contexts are compared with the FP64 oracle evaluated on
+the very state the GPU holds (exported, decoded exactly to FP64).  The only
+difference left is then the GPU's FP32 arithmetic, so the bars are error
+bounds of that arithmetic, per cell, from the exported populations:
+
+* rho - rho0 is a sum of 19 stored shifts h_i: |error| <= 20 u S with
+  u = 2^-24 and S = sum_i |h_i| (recursive summation), plus one rounding of
+  rho0 + (rho - rho0);
+* u = j / rho with j a sum of shifts: |error| <= (20 u S + |u| B_rho) / rho
+  plus a few units of |u| (hardware reciprocal, products);
+* nu_t = (tau_eff - tau0)/3 depends on Q with slope at most
+  K / (12 tau0 rho), K = 18 (C Delta)^2, and Q on the second moments, each a
+  sum of shifts (|error| <= 20 u S) minus rho u u; 150 u S bounds |dQ|.
+
+The mass is compared at 82M cells with an FP64 sum of the exported state,
+and the watchdog with a NaN, a corrupt checkpoint and an unstable run.
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import fluid_mask, oracle_for
+from paper_2607_04516_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+binding = pytest.importorskip("paper_2607_04516_amd.binding")
+
+U32 = 2.0 ** -24
+W_ = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _bounds(f, w, tau0, c_smag):
+    """Per-cell error bounds (B_rho, B_u, B_nut) of FP32 moments of the
+    populations f [19, nz, ny, nx] (see the module docstring)."""
+    h = f - W_[:, None, None, None]
+    S = np.abs(h).sum(0)
+    rho = f.sum(0)
+    c = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 0],
+                  [-1, -1, 0], [1, 0, 1], [-1, 0, -1], [0, 1, 1], [0, -1, -1], [1, -1, 0], [-1, 1, 0],
+                  [1, 0, -1], [-1, 0, 1], [0, 1, -1], [0, -1, 1]], np.float64)
+    u = np.einsum("ia,i...->a...", c, f) / rho
+    umag = np.sqrt((u * u).sum(0))
+    b_rho = 20 * U32 * S + 2 * U32
+    b_u = (20 * U32 * S + umag * b_rho) / rho + 8 * U32 * umag
+    K = 18.0 * c_smag ** 2
+    b_nut = K / (12 * tau0 * rho) * 150 * U32 * S + 8 * U32
+    return b_rho, b_u, b_nut, S
+
+
+def _state_f64(lat):
+    st, t = lat.get_state()
+    torch.cuda.synchronize()
+    return lat.state_to_f64(st), t
+
+
+@pytest.mark.parametrize("steps", [36, 37])
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_subdomain_diagnostics_reduced_precision(storage, steps):
+    """128x128x64 urban subdomain: macros, mass, energy and point probes of
+    the GPU state against the oracle on the exported state."""
+    print(f"case: urban subdomain 128x128x64 {storage}, diagnostics after {steps} steps", flush=True)
+    w = workloads.urban_subdomain(storage, steps)
+    lat = binding.from_workload(w)
+    lat.step(steps)
+    f, _ = _state_f64(lat)
+    o = oracle_for(w)
+    ro, uo, no = o.macros(f)
+    mo, eo = o.mass(f)
+    rg, ug, ng = [t.double().cpu().numpy() for t in lat.macros()]
+    b_rho, b_u, b_nut, S = _bounds(f, w, w.tau0, w.c_smag)
+    m = fluid_mask(w)
+    for name, got, ref, bar in (("rho", rg, ro, b_rho), ("nu_t", ng, no, b_nut)):
+        err = np.abs(got - ref)[m]
+        print(f"{storage} {name}: max |d| {err.max():.3e}, max |d| / bound {(err / bar[m]).max():.3f}", flush=True)
+        assert np.all(err <= bar[m]), name
+    err_u = np.abs(ug - uo)[:, m]
+    print(f"{storage} u: max |d| {err_u.max():.3e}, max |d| / bound {(err_u / b_u[m]).max():.3f}", flush=True)
+    assert np.all(err_u <= b_u[m])
+    # inflow and solid cells report their defined values exactly
+    inflow_cells = ~m & ~w.solid.astype(bool)
+    np.testing.assert_allclose(ug[:, inflow_cells], uo[:, inflow_cells], rtol=0, atol=1e-7)
+    assert np.all(ug[:, w.solid.astype(bool)] == 0)
+    # mass and energy over the fluid cells
+    mg, eg = lat.mass()
+    bm = float((20 * U32 * S)[m].sum() + 2 * U32 * np.abs(ro - 1)[m].sum())
+    rho_m, u_m = ro[m], np.sqrt((uo[:, m] ** 2).sum(0))
+    be = float((rho_m * u_m * b_u[m] + 0.5 * u_m ** 2 * b_rho[m]).sum()) + 1e-12 * eo
+    print(f"{storage} mass: |d| {abs(mg - mo):.3e} (bound {bm:.3e}); energy: |d| {abs(eg - eo):.3e} "
+          f"(bound {be:.3e}, E {eo:.4e})", flush=True)
+    assert abs(mg - mo) <= bm
+    assert abs(eg - eo) <= be
+    # point probes at fluid cells (host float output: one more rounding)
+    rng = np.random.default_rng(steps)
+    zz, yy, xx = np.nonzero(m)
+    k = rng.choice(len(zz), 64, replace=False)
+    pts = np.stack([xx[k], yy[k], zz[k]], 1).astype(np.float64)
+    out = lat.probe(pts).astype(np.float64)
+    for j, (x, y, z) in enumerate(pts.astype(int)):
+        assert abs(out[j, 0] - ro[z, y, x]) <= b_rho[z, y, x] + U32 * ro[z, y, x]
+        du = np.abs(out[j, 1:] - uo[:, z, y, x])
+        assert np.all(du <= b_u[z, y, x] + U32 * np.abs(uo[:, z, y, x])), (x, y, z, du)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_probe_accumulator_and_stats_reduced_precision(storage):
+    """The compensated probe accumulator (lbm_step_probed) and the time
+    statistics of the step kernels over 12 steps against the oracle's u at
+    each exported state; bars: the sum of the per-step bounds."""
+    print(f"case: urban subdomain 128x128x64 {storage}, probe accumulator and stats over 12 steps", flush=True)
+    w = workloads.urban_block(storage, 12, 128, 128, 64, hmax=48, nprobes=32, seed=2, probe_seed=3, noise_seed=4)
+    lat = binding.from_workload(w)
+    lat.step(30)
+    probes = np.asarray(w.probes, np.int64)
+    lat.set_probes(probes)
+    acc = torch.zeros(2, len(probes), 3, dtype=torch.float32, device="cuda")
+    stats = torch.zeros(6, w.nz, w.ny, w.nx, dtype=torch.float32, device="cuda")
+    lat.set_stats(stats, 3)
+    o = oracle_for(w)
+    ref_acc = np.zeros((len(probes), 3))
+    bar_acc = np.zeros((len(probes), 3))
+    ref_st = np.zeros((6, w.nz, w.ny, w.nx))
+    bar_st = np.zeros((6, w.nz, w.ny, w.nx))
+    solid = w.solid.astype(bool)
+    for t in range(30, 42):
+        f, tt = _state_f64(lat)
+        assert tt == t
+        _, uo, _ = o.macros(f)
+        uo[:, solid] = 0.0
+        _, b_u, _, _ = _bounds(f, w, w.tau0, w.c_smag)
+        b_u[~fluid_mask(w)] = 1e-7        # inflow cells: u_in rounded to FP32
+        if t % 3 == 0:
+            ref_st[:3] += uo
+            ref_st[3:] += uo * uo
+            bar_st[:3] += b_u
+            bar_st[3:] += 2 * np.abs(uo) * b_u + b_u ** 2
+        lat.step_probed(1, acc)
+        f1, _ = _state_f64(lat)
+        _, u1, _ = o.macros(f1)
+        _, b1, _, _ = _bounds(f1, w, w.tau0, w.c_smag)
+        ref_acc += u1[:, probes[:, 2], probes[:, 1], probes[:, 0]].T
+        bar_acc += b1[probes[:, 2], probes[:, 1], probes[:, 0]][:, None]
+    lat.set_stats(None, 0)
+    got_acc = (acc[0].double() + acc[1].double()).cpu().numpy()
+    err = np.abs(got_acc - ref_acc)
+    print(f"{storage} probe accumulator: max |d| {err.max():.3e}, max |d| / bound {(err / bar_acc).max():.3f}",
+          flush=True)
+    assert np.all(err <= bar_acc + 12 * U32 * np.abs(ref_acc))
+    got_st = stats.double().cpu().numpy()
+    err = np.abs(got_st - ref_st)
+    bar = bar_st + 4 * U32 * np.abs(ref_st)
+    print(f"{storage} stats: max |d| {err.max():.3e}, max |d| / bound {(err / bar).max():.3f}", flush=True)
+    assert np.all(err <= bar)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_kilometre_grid_mass_against_fp64_sum(storage):
+    """82M cells: lbm_mass against an FP64 sum of the exported state over the
+    fluid cells; bar: the FP32 per-cell moment bound summed over the cells."""
+    print(f"case: urban_km 800x800x128 {storage}, mass vs FP64 sum of the exported state", flush=True)
+    w = workloads.urban_km(storage, 12)
+    lat = binding.from_workload(w)
+    lat.step(12)
+    st, _ = lat.get_state()
+    m = torch.from_numpy(fluid_mask(w)).cuda()
+    total = torch.zeros((), dtype=torch.float64, device="cuda")
+    s_abs = torch.zeros((), dtype=torch.float64, device="cuda")
+    for i in range(19):
+        hi = st[i].double() / lat.scale
+        total += hi[m].sum()
+        s_abs += hi[m].abs().sum()
+    n_fluid = int(m.sum())
+    ref = n_fluid * 1.0 + float(total)
+    mg, eg = lat.mass()
+    bound = 20 * U32 * float(s_abs) + 1e-9 * n_fluid * U32
+    print(f"{storage}: mass {mg:.10e} vs FP64 {ref:.10e}: |d| {abs(mg - ref):.3e}, bound {bound:.3e}", flush=True)
+    assert abs(mg - ref) <= bound
+    assert np.isfinite(eg) and eg > 0
+
+
+# --------------------------------------------------------------------------- watchdog
+def _cube_small(tau0=0.52, u=0.05, c_smag=0.1):
+    nx, ny, nz = 32, 24, 16
+    solid = workloads.cube_mask(nx, ny, nz, x0=8, size=(4, 4, 6))
+    prof = workloads.uniform_profile(nz, (u, 0.0, 0.0))
+    return workloads.Workload("cube_small", nx, ny, nz, workloads.FACES_CHANNEL, tau0, c_smag, "f32", 10, solid,
+                              {0: prof}, prof.copy(), noise_seed=1)
+
+
+def test_watchdog_nan_through_set_state():
+    w = _cube_small()
+    lat = binding.from_workload(w, watchdog_stride=1)
+    lat.step(3)
+    st, t = lat.get_state()
+    st[4, 8, 12, 20] = float("nan")          # a fluid cell
+    with pytest.raises(binding.LBMError) as e:
+        lat.set_state(st, t)
+    assert e.value.code == -4 and "nonfinite=1" in str(e.value)
+    # without the watchdog the import succeeds and the first checked step fails
+    lat2 = binding.from_workload(w)
+    lat2.set_state(st, t)
+    lat2.close()
+
+
+def test_watchdog_corrupt_checkpoint():
+    """A checkpoint whose cell carries rho - rho0 = 0.9 is refused at import."""
+    w = _cube_small()
+    lat = binding.from_workload(w, watchdog_stride=5)
+    st, t = lat.get_state()
+    st[:, 8, 12, 20] = torch.tensor(W_ * 0.9, dtype=st.dtype, device=st.device)
+    with pytest.raises(binding.LBMError) as e:
+        lat.set_state(st, t)
+    assert e.value.code == -4 and "max|rho-rho0|=0.9" in str(e.value)
+
+
+def test_watchdog_unstable_run():
+    """tau0 just above 1/2 without the eddy viscosity and inflow at 0.25:
+    the run leaves the stable range within tens of steps (the oracle reaches
+    |rho - 1| > 0.5 before step 40); the watchdog stops it with EUNSTABLE."""
+    w = _cube_small(tau0=0.5001, u=0.25, c_smag=0.0)
+    lat = binding.from_workload(w, watchdog_stride=10)
+    with pytest.raises(binding.LBMError) as e:
+        lat.step(2000)
+    assert e.value.code == -4
+    assert 0 < lat.time <= 200, lat.time
+    print(f"watchdog fired at t = {lat.time}: {e.value}", flush=True)
+
+
+def test_watchdog_quiet_on_a_stable_run():
+    w = _cube_small()
+    lat = binding.from_workload(w, watchdog_stride=7)
+    lat.step(50)
+    assert lat.time == 50
