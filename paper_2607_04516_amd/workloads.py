@@ -25,6 +25,9 @@ FACE_NAMES = ("periodic", "inflow", "outflow", "freeslip", "wall")
 
 FACES_CHANNEL = ("inflow", "outflow", "freeslip", "freeslip", "wall", "freeslip")
 FACES_TWO_INLETS = ("inflow", "outflow", "inflow", "outflow", "wall", "freeslip")
+# the paper's open domain (Sec. 2.3): equilibrium velocity on the four lateral
+# faces and the top, no-slip ground
+FACES_OPEN = ("inflow", "inflow", "inflow", "inflow", "wall", "inflow")
 
 
 # --------------------------------------------------------------------------
@@ -182,6 +185,20 @@ def urban_km(storage="f32", steps=5000, nx=800, ny=800, nz=128, seed=5, noise_se
     return Workload(f"urban_km_{nx}x{ny}x{nz}", nx, ny, nz, FACES_TWO_INLETS, 0.505, 0.1,
                     storage, steps, heights_to_mask(h, nz), {0: prof, 2: prof.copy()},
                     prof.copy(), noise_seed=noise_seed, heights=h)
+
+
+def urban_km_open(storage="f32", steps=5000, sponge=(16, 0.05)):
+    """The kilometre grid with the paper's open boundaries (Sec. 2.3): the
+    30-degree power-law profile as the boundary state of all four lateral
+    faces and the top (equilibrium velocity faces), no-slip ground, and the
+    relaxation layers (width, strength) next to those faces."""
+    w = urban_km(storage, steps)
+    w.name = "urban_km_open_800x800x128"
+    w.faces = FACES_OPEN
+    prof = w.inflow[0]
+    w.inflow = {F: prof.copy() for F in (0, 1, 2, 3, 5)}
+    w.sponge = sponge
+    return w
 
 
 def urban_subdomain(storage="f16s", steps=100):

@@ -64,7 +64,7 @@ def _fd(prob, speeds, theta, target, h=1e-4, comps=None):
             else:
                 th += sgn * h
             ub, _ = prob.run_forward(sp, th, keep_checkpoints=False)
-            vals.append(float(((ub - target) ** 2).sum()))
+            vals.append(float(((ub - target.to(ub.device, ub.dtype)) ** 2).sum()))
         out[k] = (vals[0] - vals[1]) / (2 * h)
     return out
 
