@@ -251,6 +251,18 @@ int lbm_macros(lbm_ctx *ctx, void *rho, void *u, void *nu_t);
  * outside [0, n-1] are clamped.  Synchronises. */
 int lbm_probe(lbm_ctx *ctx, const float *pts, int32_t np, float *out);
 
+/* lbm_probe for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sampling, arguments and results, staged through a fixed per-GPU
+ * scratch array of LBM_PROBE_NOALLOC_MAX * 7 floats (448 KiB) that the
+ * library holds until the process ends, so the call makes no hipMalloc,
+ * hipFree or other allocating call.  np > LBM_PROBE_NOALLOC_MAX returns
+ * LBM_EINVAL.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (several host threads, or contexts on different
+ * streams) race and must be serialised by the caller.  Synchronises. */
+#define LBM_PROBE_NOALLOC_MAX 16384
+int lbm_probe_noalloc(lbm_ctx *ctx, const float *pts, int32_t np, float *out);
+
 /* Mass sum(rho) and kinetic energy sum(rho |u|^2 / 2) over fluid cells
  * (solid and inflow cells excluded).  Per-lane compensated sums of
  * rho - rho0 in real precision, then a deterministic double-precision tree

@@ -24,6 +24,8 @@ STORE_SCALE = {F64: 1.0, F32: 1.0, F16S: 256.0, BF16S: 1.0}
 
 FACE_KIND = {"periodic": 0, "inflow": 1, "outflow": 2, "freeslip": 3, "wall": 4, "halo": 5}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSTABLE", -5: "ESTATE"}
+LBM_EINVAL = -1
+LBM_PROBE_NOALLOC_MAX = 16384   # include/lbm.h: points per lbm_probe_noalloc call
 
 # D3Q19 weights in the library's direction order (for h <-> f conversions)
 WEIGHTS = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
@@ -59,7 +61,7 @@ EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_inflow_face",
            "lbm_set_turbulence",
            "lbm_turbulence_info", "lbm_get_inflow", "lbm_set_sponge", "lbm_balance_flux", "lbm_net_flux",
            "lbm_reset", "lbm_step", "lbm_step_probed",
-           "lbm_macros", "lbm_probe", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
+           "lbm_macros", "lbm_probe", "lbm_probe_noalloc", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
            "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read",
            "lbm_halo_pack", "lbm_halo_unpack", "lbm_voxelize"]
@@ -97,6 +99,7 @@ def load(path: str = LIB_PATH):
         "lbm_step_probed": ([P, I64, P], ctypes.c_int),
         "lbm_macros": ([P, P, P, P], ctypes.c_int),
         "lbm_probe": ([P, P, I32, P], ctypes.c_int),
+        "lbm_probe_noalloc": ([P, P, I32, P], ctypes.c_int),
         "lbm_mass": ([P, P, P], ctypes.c_int),
         "lbm_get_state": ([P, P, ctypes.POINTER(I64)], ctypes.c_int),
         "lbm_set_state": ([P, P, I64], ctypes.c_int),
@@ -314,6 +317,14 @@ class LBM:
         out = np.zeros((pts.shape[0], 4), np.float32)
         self._check(self.lib.lbm_probe(self.ctx, pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0],
                                        out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def probe_noalloc(self, pts):
+        """lbm_probe through the library's fixed per-GPU scratch (no device allocation)."""
+        pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+        out = np.zeros((pts.shape[0], 4), np.float32)
+        self._check(self.lib.lbm_probe_noalloc(self.ctx, pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0],
+                                               out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def mass(self):

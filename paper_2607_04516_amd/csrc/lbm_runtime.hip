@@ -11,11 +11,25 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace lbm;
+
+// Device scratch of lbm_probe_noalloc: the staged probe points [np][3]
+// followed by their results [np][4] (floats), one copy per GPU, held until
+// the process ends.  Host code never uses the array's name as an address:
+// lbm_create looks up each device's copy with hipGetSymbolAddress (device
+// current) and keeps the pointer per device.
+static __device__ __align__(256) float scratch[LBM_PROBE_NOALLOC_MAX * 7];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+}  // namespace
 
 struct lbm_ctx {
     DevCtx d;
@@ -283,6 +297,23 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, LBM_EHIP, "no HIP device");
+    }
+    if (c->device < 0 || c->device >= kMaxDevices) {
+        delete c;
+        return fail(nullptr, LBM_EINVAL, "device ordinal beyond the library's limit");
+    }
+    {
+        // this device's copy of the lbm_probe_noalloc scratch (once per device)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[c->device]) {
+            void* ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) {
+                delete c;
+                return fail(nullptr, LBM_EHIP, std::string("scratch lookup: ") + hipGetErrorString(e));
+            }
+            g_scratch[c->device] = (float*)ptr;
+        }
     }
     {
         int lds = 0;
@@ -892,6 +923,32 @@ int lbm_probe(lbm_ctx* c, const float* pts, int32_t np, float* out)
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(dbuf);
     if (e != hipSuccess) return hip_fail(c, e, "probe");
+    return LBM_OK;
+}
+
+int lbm_probe_noalloc(lbm_ctx* c, const float* pts, int32_t np, float* out)
+{
+    if (!c) return LBM_EINVAL;
+    if (np < 0 || (np > 0 && (!pts || !out))) return fail(c, LBM_EINVAL, "bad probe arguments");
+    if (np > LBM_PROBE_NOALLOC_MAX)
+        return fail(c, LBM_EINVAL, "np = " + std::to_string(np) + " exceeds LBM_PROBE_NOALLOC_MAX (" +
+                                       std::to_string(LBM_PROBE_NOALLOC_MAX) + ")");
+    if (np == 0) return LBM_OK;
+    for (int i = 0; i < 3 * np; i++)
+        if (!std::isfinite(pts[i])) return fail(c, LBM_EINVAL, "non-finite probe coordinate");
+    float* dbuf;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        dbuf = g_scratch[c->device];
+    }
+    if (!dbuf) return fail(c, LBM_ESTATE, "no scratch address for this device");
+    // points in, results out: every value the kernel reads is written first
+    hipError_t e = hipMemcpyAsync(dbuf, pts, (size_t)np * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_probe_points(c->d, c->phase, dbuf, np, dbuf + 3 * (size_t)np, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, dbuf + 3 * (size_t)np, (size_t)np * 4 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "probe (no allocation)");
     return LBM_OK;
 }
 

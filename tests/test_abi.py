@@ -37,6 +37,13 @@ def test_binding_lists_every_symbol():
     assert sorted(binding.EXPORTS) == declared()
 
 
+def test_binding_constants_match_header():
+    from paper_2607_04516_amd import binding
+    src = open(HEADER).read()
+    assert int(re.search(r"#define LBM_PROBE_NOALLOC_MAX (\d+)", src).group(1)) == binding.LBM_PROBE_NOALLOC_MAX
+    assert int(re.search(r"#define LBM_EINVAL \((-\d+)\)", src).group(1)) == binding.LBM_EINVAL
+
+
 def test_params_struct_layout():
     from paper_2607_04516_amd import binding
     P = binding._Params
