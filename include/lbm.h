@@ -91,8 +91,12 @@ typedef struct {
  * (buildings and terrain voxels, Sec. 2.1); copied and bit-packed on the
  * device.  Allocates the population array (19 * nx_pitch * ny * nz * sizeof(store))
  * and initialises the state at t = 0 to feq(rho0, u_init + noise) in fluid
- * cells and h = 0 in solid cells.  Errors: EINVAL, ENOMEM, EHIP; *out is
- * NULL on error and lbm_last_error(NULL) gives the message. */
+ * cells and h = 0 in solid cells.  Size limit: one population slice
+ * (nx_pitch * ny * nz * sizeof(store), nx_pitch = nx rounded up to 64) must
+ * stay below 2 GiB, or below 512 MiB when a y or z face is LBM_FREESLIP or
+ * LBM_HALO (the kernels' 32-bit slot offsets span up to eight slices there);
+ * larger grids return EINVAL.  Errors: EINVAL, ENOMEM, EHIP; *out is NULL on
+ * error and lbm_last_error(NULL) gives the message. */
 int lbm_create(const lbm_grid *grid, const uint8_t *solid, const lbm_params *params, lbm_ctx **out);
 
 /* Set the velocity profile of an INFLOW_EQ face: host double [nz][3]; every
@@ -130,6 +134,16 @@ int lbm_set_inflow_face(lbm_ctx *ctx, int32_t face, const double *u);
  * lbm_adjoint_step from the next call on.  Errors: EINVAL (NULL, a
  * component not finite or of magnitude above 0.25). */
 int lbm_set_rotation(lbm_ctx *ctx, const double *omega);
+
+/* The Earth's rotation vector in lattice units for lbm_set_rotation (App. E):
+ * Omega_ENU = LBM_OMEGA_EARTH * (0, cos phi, sin phi) rad/s in the
+ * east-north-up frame at latitude phi = latitude_deg, times the time step
+ * dt_si in seconds, expressed in grid axes whose x axis is turned
+ * counterclockwise from east by grid_angle_deg (y likewise from north; z up).
+ * out: host double [3].  Host arithmetic only, no context.  Errors: EINVAL
+ * (NULL out, an argument not finite, dt_si <= 0, |latitude_deg| > 90). */
+#define LBM_OMEGA_EARTH 7.292115e-5
+int lbm_earth_rotation(double latitude_deg, double dt_si, double grid_angle_deg, double *out);
 
 /* Synthetic von Karman inflow turbulence (App. F).  Before every step from
  * time t the boundary velocity of each active cell becomes

@@ -58,7 +58,7 @@ class _Turbulence(ctypes.Structure):
 
 
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_inflow_face", "lbm_set_rotation",
-           "lbm_set_turbulence",
+           "lbm_earth_rotation", "lbm_set_turbulence",
            "lbm_turbulence_info", "lbm_get_inflow", "lbm_set_sponge", "lbm_balance_flux", "lbm_net_flux",
            "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_probe_noalloc", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
         "lbm_voxelize": ([ctypes.POINTER(_Grid), P, I32, P, I32, I32, P], ctypes.c_int),
         "lbm_halo_unpack": ([P, I32, P], ctypes.c_int),
         "lbm_set_rotation": ([P, P], ctypes.c_int),
+        "lbm_earth_rotation": ([ctypes.c_double, ctypes.c_double, ctypes.c_double, P], ctypes.c_int),
         "lbm_set_turbulence": ([P, ctypes.POINTER(_Turbulence)], ctypes.c_int),
         "lbm_turbulence_info": ([P, P, P, P], ctypes.c_int),
         "lbm_get_inflow": ([P, I32, P], ctypes.c_int),
@@ -416,19 +417,16 @@ def voxelize(shape, tris, starts, passes=1, solid=None):
     return out
 
 
-OMEGA_EARTH = 7.292115e-5   # rad/s (App. E)
+OMEGA_EARTH = 7.292115e-5   # rad/s, include/lbm.h LBM_OMEGA_EARTH (App. E)
 
 
-def earth_rotation(latitude_deg: float, dt_si: float, grid_angle_deg: float = 0.0,
-                   omega_si: float = OMEGA_EARTH) -> np.ndarray:
-    """Rotation vector in lattice units for a grid at the given latitude
-    (App. E): Omega_ENU = Omega (0, cos phi, sin phi) in the east-north-up
-    frame, times the time step dt_si in seconds.  grid_angle_deg turns the
-    grid's x axis counterclockwise from east (the grid axes are east and
-    north turned by that angle), and the vector is expressed in grid axes."""
-    p = np.radians(latitude_deg)
-    enu = omega_si * dt_si * np.array([0.0, np.cos(p), np.sin(p)])
-    a = np.radians(grid_angle_deg)
-    ex = np.array([np.cos(a), np.sin(a), 0.0])     # grid x in ENU
-    ey = np.array([-np.sin(a), np.cos(a), 0.0])    # grid y in ENU
-    return np.array([enu @ ex, enu @ ey, enu[2]])
+def earth_rotation(latitude_deg: float, dt_si: float, grid_angle_deg: float = 0.0) -> np.ndarray:
+    """lbm_earth_rotation: the Earth's rotation vector in lattice units in
+    grid axes (App. E), for set_rotation."""
+    lib = load()
+    out = np.zeros(3, np.float64)
+    rc = lib.lbm_earth_rotation(float(latitude_deg), float(dt_si), float(grid_angle_deg),
+                                out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise LBMError(rc, lib.lbm_last_error(None).decode())
+    return out

@@ -115,6 +115,19 @@ static inline StepOff step_offsets(long long slice, long long rowlen, long long 
     return o;
 }
 
+// Slices spanned by the two candidate slots of one direction (own slot I and
+// pull-source slot opp(I')), plus one for the lane offset inside a slice: 2
+// when every row class is plain (opp(I) is next to I), 8 when a y or z face
+// is FREESLIP (the remapped directions of its face rows reach up to seven
+// slices away, e.g. 7 -> 14 in the y = 0 row).  The 32-bit slot offsets need
+// span * (slice bytes) < 2^32.
+__host__ __device__ inline long long slot_span(const int face[6])
+{
+    for (int k = 2; k < 6; k++)
+        if (face[k] == F_FREESLIP) return 8;
+    return 2;
+}
+
 typedef const StepOff __attribute__((address_space(4))) const_stepoff;
 
 // The offsets of one row class from a per-context table of nine.

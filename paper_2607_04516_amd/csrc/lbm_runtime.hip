@@ -282,11 +282,18 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     }
     const long long N = (long long)grid->nx * grid->ny * grid->nz;
     {
-        // the step kernels address two adjacent slices with 32-bit byte offsets
+        // the step kernels address the two candidate slots of a direction with
+        // 32-bit byte offsets from the lower slice (slot_span slices apart at
+        // most: two, or eight with FREESLIP y or z faces, HALO rows included)
+        int kinds[6];
+        for (int k = 0; k < 6; k++) kinds[k] = params->face[k] == LBM_HALO ? F_FREESLIP : params->face[k];
+        const long long span = slot_span(kinds);
         const long long pitch = ((long long)grid->nx + 63) / 64 * 64;
         const long long slice = pitch * grid->ny * grid->nz * (long long)codec_bytes(params->storage);
-        if (2 * slice >= (1ll << 32) || (long long)grid->ny * grid->nz * (((long long)grid->nx + 63) / 64) >= (1ll << 32))
-            return fail(nullptr, LBM_EINVAL, "grid too large for one context (a population slice must stay below 2 GiB)");
+        if (span * slice >= (1ll << 32) || (long long)grid->ny * grid->nz * (((long long)grid->nx + 63) / 64) >= (1ll << 32))
+            return fail(nullptr, LBM_EINVAL,
+                        "grid too large for one context (a population slice must stay below " +
+                            std::string(span == 2 ? "2 GiB" : "512 MiB with free-slip y or z faces") + ")");
     }
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
@@ -612,6 +619,23 @@ int lbm_set_rotation(lbm_ctx* c, const double* omega)
         if (!std::isfinite(omega[a]) || std::fabs(omega[a]) > 0.25)
             return fail(c, LBM_EINVAL, "rotation component not finite or beyond 0.25 per time step");
     for (int a = 0; a < 3; a++) c->d.omega[a] = omega[a];
+    return LBM_OK;
+}
+
+int lbm_earth_rotation(double latitude_deg, double dt_si, double grid_angle_deg, double* out)
+{
+    if (!out || !std::isfinite(latitude_deg) || !std::isfinite(dt_si) || !std::isfinite(grid_angle_deg) ||
+        !(dt_si > 0.0) || std::fabs(latitude_deg) > 90.0)
+        return fail(nullptr, LBM_EINVAL, "bad Earth rotation arguments");
+    // east-north-up components of Omega dt, then onto the grid axes
+    // ex = (cos a, sin a, 0), ey = (-sin a, cos a, 0) written in ENU
+    const double kPi = 3.14159265358979323846;
+    const double phi = latitude_deg * (kPi / 180.0), a = grid_angle_deg * (kPi / 180.0);
+    const double w = LBM_OMEGA_EARTH * dt_si;
+    const double north = w * std::cos(phi), up = w * std::sin(phi);
+    out[0] = north * std::sin(a);   // (0, north, up) . ex
+    out[1] = north * std::cos(a);   // (0, north, up) . ey
+    out[2] = up;
     return LBM_OK;
 }
 
@@ -1081,10 +1105,12 @@ int lbm_adjoint_step(lbm_ctx* c, const void* f_t, const void* lam_next, void* la
     if (has_halo(c)) return fail(c, LBM_ESTATE, "adjoint step on a slab");
     if (!f_t || !lam_next || !lam || lam == lam_next) return fail(c, LBM_EINVAL, "bad adjoint arguments");
     {
-        // the adjoint kernels address two adjacent adjoint slices with 32-bit byte offsets
+        // the adjoint kernels address the two candidate slots of a direction
+        // with 32-bit byte offsets (slot_span adjoint slices apart at most)
         const long long real_bytes = c->p.storage == LBM_F64 ? 8 : 4;
-        if (2 * c->d.g.N * real_bytes >= (1ll << 32))
-            return fail(c, LBM_EINVAL, "grid too large for the adjoint (an adjoint slice must stay below 2 GiB)");
+        if (slot_span(c->d.g.face) * c->d.g.N * real_bytes >= (1ll << 32))
+            return fail(c, LBM_EINVAL, "grid too large for the adjoint (an adjoint slice must stay below " +
+                                           std::string(slot_span(c->d.g.face) == 2 ? "2 GiB" : "512 MiB with free-slip y or z faces") + ")");
     }
     if (probe_src && c->np == 0) return fail(c, LBM_ESTATE, "probe source without registered probes");
     if (c->vk) return fail(c, LBM_ESTATE, "adjoint step with synthetic inflow turbulence on");

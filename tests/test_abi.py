@@ -105,3 +105,10 @@ def test_earth_rotation_vector():
     r = earth_rotation(lat, dt, grid_angle_deg=-0.911)
     assert abs(np.linalg.norm(r) - OMEGA_EARTH * dt) <= 1e-20 and r[2] == om[2]
     assert r[0] < 0.0    # grid x turned clockwise from east has a southward part
+    # the header's constant, and the argument checks
+    src = open(HEADER).read()
+    assert float(re.search(r"#define LBM_OMEGA_EARTH ([0-9.e-]+)", src).group(1)) == OMEGA_EARTH
+    from paper_2607_04516_amd.binding import LBMError
+    for bad in ((91.0, 0.01), (23.0, 0.0), (float("nan"), 0.01)):
+        with pytest.raises(LBMError):
+            earth_rotation(*bad)
