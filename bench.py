@@ -411,7 +411,7 @@ def main():
         "config": {"workload": f"{w.name}: urban buildings PAF 0.30, median 12, power-law inflow 30 deg "
                                f"on x-/y-, outflow x+/y+, wall ground, free-slip top, tau0 0.505, C 0.1",
                    "cells": w.cells, "fluid_cells": res["fluid_cells"], "storage": args.storage,
-                   "layout": "SoA [19][z][y][x_pitch64], in-place A-A"},
+                   "layout": "row blocks [ny*nz/32][19][32 rows][x_pitch64], in-place A-A"},
         "roofline": {"bound": "hbm", "achieved": round(res["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (res["kernel_ms"] * 1e-3) / 1e9, 1),

@@ -30,13 +30,11 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
 {
     using C = Codec<K>;
     using R = typename C::real;
-    const long long ns = cell_index(ls, g.ny, x, y, z);
-    const long long nd = cell_index(ld, g.ny, x, y, z);
     if (solid_at(mask, g, x, y, z)) {
         if constexpr (MODE == MODE_PUSH) {
             static_for<0, NQ>([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
-                dst[(long long)I * ld.S + nd] = C::enc(R(0));
+                dst[pop_index(ld, g.ny, I, x, y, z)] = C::enc(R(0));
             });
         }
         return;
@@ -53,17 +51,17 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             if constexpr (MODE == MODE_EVEN) {
-                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
+                dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[opp(I)]);
             } else if constexpr (MODE == MODE_PUSH) {
                 // canonical output of an inflow cell is its own equilibrium
-                dst[(long long)I * ld.S + nd] = C::pack(h[I]);
+                dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[I]);
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
-                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                    dst[pop_index(ld, g.ny, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
             } else {
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0)
-                    dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                    dst[pop_index(ld, g.ny, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
             }
         });
     } else {
@@ -76,10 +74,10 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
                     h[I] = C::raw(ghost[ghost_index<I>(g, owner, x, y, z)]);
                 } else {
                     const Res r = resolve_plain<I>(g, mask, x, y, z);
-                    h[I] = C::raw(src[(long long)r.dir * ls.S + cell_index(ls, g.ny, r.x, r.y, r.z)]);
+                    h[I] = C::raw(src[pop_index(ls, g.ny, r.dir, r.x, r.y, r.z)]);
                 }
             } else {
-                h[I] = C::raw(src[(long long)I * ls.S + ns]);
+                h[I] = C::raw(src[pop_index(ls, g.ny, I, x, y, z)]);
             }
         });
         R drho, tau;
@@ -88,20 +86,20 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             if constexpr (MODE == MODE_EVEN) {
-                dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
+                dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[opp(I)]);
             } else {
                 int qx, qy, qz, owner;
                 if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
                     // opp(I) leaves through the outflow face: kept only as the
                     // bounce-back of a solid inner neighbour
-                    if (solid_at(mask, g, qx, qy, qz)) dst[(long long)I * ld.S + nd] = C::pack(h[opp(I)]);
+                    if (solid_at(mask, g, qx, qy, qz)) dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[opp(I)]);
                 } else {
                     const Res r = resolve_plain<I>(g, mask, x, y, z);
                     if (r.kind == 0) {
                         if constexpr (MODE == MODE_PUSH) {
                             if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
                         }
-                        dst[(long long)r.dir * ld.S + cell_index(ld, g.ny, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                        dst[pop_index(ld, g.ny, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
                     }
                 }
             }

@@ -45,7 +45,7 @@ struct DevCtx {
     unsigned adj_sched_n;
     const int* wave_idx;       // per wave (chunk, row): entry in wave_tab, -1 without solid neighbour
     const uint64_t* wave_tab;  // [entries][18] solid-source masks
-    const StepOff* off_odd;    // [9] row-class offsets, padded layout, store elements
+    const StepOff* off_odd;    // [9 row classes][4 block edges] offsets of the in-place array, store elements
     const StepOff* off_push;   // [9] canonical layout, store elements
     const StepOff* off_adj;    // [9] canonical layout, real (adjoint) elements
     double tau0, c_smag, delta, rho0, force[3];
@@ -126,6 +126,63 @@ __host__ __device__ inline long long slot_span(const int face[6])
     for (int k = 2; k < 6; k++)
         if (face[k] == F_FREESLIP) return 8;
     return 2;
+}
+
+// Element offset of slot s of the cell (x + dx, row + dy + ny dz) from slot
+// 0 of (x, row) in the row-block layout of the in-place array (R = 2^lrb
+// rows per block, R dividing ny, |dy| <= 1).  A neighbour in z is ny / R
+// blocks away; a neighbour in y lies in the same block unless the row is the
+// first (edge bit 0, dy = -1) or last (edge bit 1, dy = +1) of its block,
+// where the step into the adjacent block adds -/+ 18 B (B = R pitch).
+static inline long long block_rel(long long pitch, long long ny, int lrb, int s, int dx, int dy, int dz, int edge)
+{
+    const long long R = 1ll << lrb, B = R * pitch;
+    long long o = s * B + dx + pitch * dy + (ny / R) * dz * NQ * B;
+    if (dy == -1 && (edge & 1)) o -= (NQ - 1) * B;
+    if (dy == 1 && (edge & 2)) o += (NQ - 1) * B;
+    return o;
+}
+
+// StepOff of the in-place array (row blocks) for row class cls and block
+// edge: offsets from the cell's row start (slot 0 of x = 0) in bytes; the
+// kernels add the row start to the base and x * elem as the lane offset, so
+// lo + (x elem + on) (pull source) and lo + (x elem + oo) (own slot) are
+// exact while on, oo + pitch elem < 2^32 (checked by lbm_create).
+static inline StepOff step_offsets_blocked(long long pitch, long long ny, int lrb, int elem, int cls, int edge)
+{
+    StepOff o;
+    const int my = cls / 3, mz = cls % 3;
+    for (int i = 0; i < NQ; i++) {
+        const V3 c = dirv(i);
+        int m = 0;
+        if ((my == 1 && c.y == 1) || (my == 2 && c.y == -1)) m |= 2;
+        if ((mz == 1 && c.z == 1) || (mz == 2 && c.z == -1)) m |= 4;
+        const int slot = opp(mirrored(i, m));
+        const long long own = block_rel(pitch, ny, lrb, i, 0, 0, 0, edge) * elem;
+        const long long nb =
+            block_rel(pitch, ny, lrb, slot, -c.x, (m & 2) ? 0 : -c.y, (m & 4) ? 0 : -c.z, edge) * elem;
+        const long long lo = own < nb ? own : nb;
+        o.even[i] = own;
+        o.odd[i] = nb;
+        o.lo[i] = lo;
+        o.on[i] = (uint32_t)(nb - lo);
+        o.oo[i] = (uint32_t)(own - lo);
+    }
+    return o;
+}
+
+// Byte offset of the start of row `row` (slot 0, x = 0) of the in-place array.
+__host__ __device__ inline long long row_start(const Geo& g, long long row, int elem)
+{
+    const long long rmask = (1ll << g.lrb) - 1;
+    return ((row >> g.lrb) * NQ * (rmask + 1) + (row & rmask)) * (long long)g.pitch * elem;
+}
+
+// Block-edge flags of a row (bit 0: first row of its block, bit 1: last).
+__host__ __device__ inline int block_edge(const Geo& g, long long row)
+{
+    const long long rr = row & ((1ll << g.lrb) - 1);
+    return (rr == 0 ? 1 : 0) | (rr == (1ll << g.lrb) - 1 ? 2 : 0);
 }
 
 typedef const StepOff __attribute__((address_space(4))) const_stepoff;

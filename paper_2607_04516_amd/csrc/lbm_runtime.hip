@@ -67,7 +67,7 @@ struct lbm_ctx {
     unsigned* adj_list = nullptr;
     unsigned* push_sched = nullptr;  // block order of the push launch
     unsigned* adj_sched = nullptr;   // block order of the adjoint launch
-    StepOff* offsets = nullptr;     // [27] row-class slot offsets: odd, push, adjoint
+    StepOff* offsets = nullptr;     // [54] row-class slot offsets: odd (x 4 block edges), push, adjoint
     int* wave_idx = nullptr;        // per wave: entry in wave_tab or -1
     uint64_t* wave_tab = nullptr;   // solid-source masks of waves with a solid neighbour
     void* stats = nullptr;
@@ -233,21 +233,22 @@ static int build_wave_masks(lbm_ctx* c)
     HIPCHK(c, hipStreamSynchronize(c->stream), "wave mask table");
     c->d.wave_idx = c->wave_idx;
     c->d.wave_tab = c->wave_tab;
-    // slot offsets of the nine row classes for the odd step (padded layout),
-    // the push recompute and the adjoint (canonical layout)
-    std::vector<StepOff> off(27);
+    // slot offsets of the nine row classes: the odd step (in-place row-block
+    // layout, per block edge), the push recompute and the adjoint (canonical
+    // layout)
+    std::vector<StepOff> off(54);
     const int es = (int)c->store_bytes, er = c->p.storage == LBM_F64 ? 8 : 4;
     for (int k = 0; k < 9; k++) {
-        off[k] = step_offsets(g.S, g.pitch, g.ny, es, k);
-        off[9 + k] = step_offsets(g.N, g.nx, g.ny, es, k);
-        off[18 + k] = step_offsets(g.N, g.nx, g.ny, er, k);
+        for (int e = 0; e < 4; e++) off[4 * k + e] = step_offsets_blocked(g.pitch, g.ny, g.lrb, es, k, e);
+        off[36 + k] = step_offsets(g.N, g.nx, g.ny, es, k);
+        off[45 + k] = step_offsets(g.N, g.nx, g.ny, er, k);
     }
     if ((rc = device_alloc(c, (void**)&c->offsets, off.size() * sizeof(StepOff), "slot offsets")) != LBM_OK)
         return rc;
     HIPCHK(c, hipMemcpy(c->offsets, off.data(), off.size() * sizeof(StepOff), hipMemcpyHostToDevice), "slot offsets");
     c->d.off_odd = c->offsets;
-    c->d.off_push = c->offsets + 9;
-    c->d.off_adj = c->offsets + 18;
+    c->d.off_push = c->offsets + 36;
+    c->d.off_adj = c->offsets + 45;
     return LBM_OK;
 }
 
@@ -282,18 +283,16 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     }
     const long long N = (long long)grid->nx * grid->ny * grid->nz;
     {
-        // the step kernels address the two candidate slots of a direction with
-        // 32-bit byte offsets from the lower slice (slot_span slices apart at
-        // most: two, or eight with FREESLIP y or z faces, HALO rows included)
-        int kinds[6];
-        for (int k = 0; k < 6; k++) kinds[k] = params->face[k] == LBM_HALO ? F_FREESLIP : params->face[k];
-        const long long span = slot_span(kinds);
+        // the step kernels address the two candidate slots of a direction in
+        // the in-place array with 32-bit byte offsets from the nearer one: a
+        // neighbour in z lies one plane of all 19 populations away
+        // (19 pitch ny elements), plus the block-edge and slot terms
         const long long pitch = ((long long)grid->nx + 63) / 64 * 64;
-        const long long slice = pitch * grid->ny * grid->nz * (long long)codec_bytes(params->storage);
-        if (span * slice >= (1ll << 32) || (long long)grid->ny * grid->nz * (((long long)grid->nx + 63) / 64) >= (1ll << 32))
+        const long long span =
+            (NQ * pitch * grid->ny + 40 * 32 * pitch + 2 * pitch) * (long long)codec_bytes(params->storage);
+        if (span >= (1ll << 32) || (long long)grid->ny * grid->nz * (((long long)grid->nx + 63) / 64) >= (1ll << 32))
             return fail(nullptr, LBM_EINVAL,
-                        "grid too large for one context (a population slice must stay below " +
-                            std::string(span == 2 ? "2 GiB" : "512 MiB with free-slip y or z faces") + ")");
+                        "grid too large for one context (19 populations of one xy plane must stay below 4 GiB)");
     }
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
@@ -336,6 +335,10 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     g.ncx = (g.nx + 63) / 64;
     g.pitch = g.ncx * 64;
     g.wpr = g.ncx;
+    // rows per block of the in-place array: the largest power of two up to
+    // 32 that divides ny (whole blocks per xy plane)
+    g.lrb = 0;
+    while (g.lrb < 5 && g.ny % (2 << g.lrb) == 0) g.lrb++;
     // a ghost row is updated like a free-slip face row (its values are
     // replaced or discarded by the halo exchange)
     for (int k = 0; k < 6; k++) {
@@ -1092,6 +1095,11 @@ int lbm_push_step(lbm_ctx* c, const void* src, void* dst)
     if (has_halo(c)) return fail(c, LBM_ESTATE, "push step on a slab");
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct device arrays");
     if (c->vk) return fail(c, LBM_ESTATE, "push step with synthetic inflow turbulence on");
+    // the push kernel addresses the two candidate slots of a direction in the
+    // canonical arrays with 32-bit byte offsets (slot_span slices apart at most)
+    if (slot_span(c->d.g.face) * c->d.g.N * (long long)c->store_bytes >= (1ll << 32))
+        return fail(c, LBM_EINVAL, "grid too large for the push step (a canonical slice must stay below " +
+                                       std::string(slot_span(c->d.g.face) == 2 ? "2 GiB" : "512 MiB with free-slip y or z faces") + ")");
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
     HIPCHK(c, launch_push(c->d, src, dst, c->stream), "push step");

@@ -45,8 +45,13 @@ __device__ inline long long xcd_remap(long long nblocks_padded)
     return blockIdx.x;
 }
 
-// Population traffic of the step kernels (plain loads and stores: the
-// streaming hint measured slower on gfx950 for this access pattern).
+// Population traffic of the step kernels.  The odd step and the push use
+// plain loads and stores: their pulls share the lines at chunk edges with
+// the neighbouring waves, and the streaming (non-temporal) hint made the
+// odd step 19% slower.  The even step touches each line once: with the
+// row-block layout, non-temporal loads and stores took the FP32 even step
+// from 2.54 to 2.13 ms on the kilometre grid; 16-bit storage is fastest with
+// non-temporal stores only (1.16 ms, against 1.20 with both).
 template <typename T>
 __device__ inline T ld_pop(const T* p)
 {
@@ -56,6 +61,17 @@ template <typename T>
 __device__ inline void st_pop(T* p, T v)
 {
     *p = v;
+}
+template <typename T>
+__device__ inline T ld_stream(const T* p)
+{
+    if constexpr (sizeof(T) >= 4) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename T>
+__device__ inline void st_stream(T* p, T v)
+{
+    __builtin_nontemporal_store(v, p);
 }
 
 template <typename R>
@@ -101,8 +117,8 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
     const uint64_t wrow = mask_word(mask, row * g.wpr + cx);
     if (x >= g.nx || ((wrow >> lane) & 1ull)) return;
 
-    char* base = (char*)f;
-    const uint32_t off = (uint32_t)((long long)x + (long long)g.pitch * row) * (uint32_t)sizeof(T);
+    char* base = (char*)f + row_start(g, row, (int)sizeof(T));
+    const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
     R h[NQ];
     const int inf = inflow_face_of(g, x, y, z);
     if (inf >= 0) {
@@ -113,19 +129,19 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
         }
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            st_pop((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
+            st_stream((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
         });
         return;
     }
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        h[I] = C::raw(ld_pop((const T*)(base + O.even[I] + off)));
+        h[I] = C::raw(ld_stream((const T*)(base + O.even[I] + off)));
     });
     R drho, ux, uy, uz, tau;
     collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        st_pop((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
+        st_stream((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
 }
@@ -156,7 +172,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
     const int y = (int)(row % g.ny), z = (int)(row / g.ny);
     if (odd_general_wave(g, cx, y, z)) return;
     const int x = cx * 64 + lane;
-    const auto& O = class_offsets(otab, row_class(g, y, z));
+    const auto& O = class_offsets(otab, 4 * row_class(g, y, z) + block_edge(g, row));
     const bool x_lo = (cx == 0);                   // lane 0 is an x- inflow or wall cell
     const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane l_out is an x+ outflow or wall cell
     const int l_out = (g.nx - 1) - cx * 64;
@@ -197,8 +213,8 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
         return m;
     };
 
-    char* base = (char*)f;
-    const uint32_t off = (uint32_t)((long long)x + (long long)g.pitch * row) * (uint32_t)sizeof(T);
+    char* base = (char*)f + row_start(g, row, (int)sizeof(T));
+    const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
     R h[NQ];
     if (!solid_any && !x_lo && !x_hi) {
         // fast path: no solid neighbour, no face lane
@@ -324,7 +340,7 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
         if (t >= ncells) return;
         const long long n = cells[t];
         const long long r = n / g.nx;
-        const Lay L{g.N, g.nx};
+        const Lay L{g.N, g.nx, -1};
         general_cell<K, MODE_PUSH, false>(dst, src, mask, uin, nullptr, g, L, L, P, nullptr, (int)(n % g.nx),
                                           (int)(r % g.ny), (int)(r / g.ny));
         return;
@@ -485,7 +501,7 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
     const Phys<R> P = phys_of<K>(d);
-    const StepOff O = step_offsets(d.g.S, d.g.pitch, d.g.ny, (int)sizeof(typename C::store));
+    const StepOff O = step_offsets_blocked(d.g.pitch, d.g.ny, d.g.lrb, (int)sizeof(typename C::store), 0, 0);
     auto* f = (typename C::store*)d.f;
     if (!odd) {
         if (stats)

@@ -2,13 +2,17 @@
 
 The fast odd, push and adjoint kernels address a population slot as
 base + lo[I] + (off + on[I] mod 2^32) (neighbour) or base + lo[I] +
-(off + oo[I] mod 2^32) (own slot), with off the cell's byte offset in its
-slice and the offsets of lbm_launch.h's step_offsets table for the row's
-class (free-slip face rows remap the crossing directions).  A host program
-compiled against the library's own header enumerates, for every row class
-and storage width, on grids from 3x3x3 to ones whose slices sit just below
-the size limit (2 GiB, or 512 MiB with free-slip y or z faces, whose face
-rows remap directions up to seven slices away), the cells of rows of that class (x-face cells included), and
+(off + oo[I] mod 2^32) (own slot), with the offsets of lbm_launch.h's tables
+for the row's class (free-slip face rows remap the crossing directions) and,
+in the in-place array's row-block layout, for the row's place at a block
+edge; base includes the row start there (row_start) and off is x times the
+element size, while in the canonical arrays of the push and adjoint off is
+the cell's byte offset in its slice.  A host program
+compiled against the library's own header enumerates, for every row class,
+block edge and storage width, on grids from 3x3x3 to ones at the size
+limits (canonical slices below 2 GiB, or 512 MiB with free-slip y or z
+faces, whose face rows remap directions up to seven slices away; in-place
+arrays of tens of GiB), the cells of rows of that class (x-face cells included), and
 checks every address the kernels can form against an independent 64-bit
 computation of the intended slot: the own slot I of the cell, and slot
 opp(I') of the pull source x - c' (c' = c_I with the components mirrored at
@@ -16,7 +20,7 @@ the row's free-slip faces zeroed) whenever that source lies in the grid.
 Every address must also fall inside the population array.  The adjoint's
 outflow copies (one element further along x) and the push's inflow-cell
 store toward x = 1 are covered by the same enumeration.  Also: lbm_create
-refuses grids beyond that limit.
+refuses grids beyond its limit.
 """
 import ctypes
 import os
@@ -44,38 +48,62 @@ static int find(int x, int y, int z) { for (int i = 0; i < 19; i++) if (D[i][0] 
 static int opposite(int i) { return find(-D[i][0], -D[i][1], -D[i][2]); }
 
 static long long errors = 0, checked = 0;
-static void fail(const char* what, int nx, int ny, int nz, int e, int cls, int x, int y, int z, int I,
-                 long long got, long long want)
+static void fail(const char* what, const Geo& g, int e, int cls, int x, int y, int z, int I, long long got, long long want)
 {
     if (errors < 20)
-        std::printf("FAIL %s grid %dx%dx%d elem %d class %d cell (%d,%d,%d) dir %d: %lld vs %lld\n", what, nx, ny, nz,
-                    e, cls, x, y, z, I, got, want);
+        std::printf("FAIL %s grid %dx%dx%d elem %d class %d cell (%d,%d,%d) dir %d: %lld vs %lld\n", what, g.nx, g.ny,
+                    g.nz, e, cls, x, y, z, I, got, want);
     errors++;
 }
 
-// one layout: slice stride (elements), row length, elements of one value
-static void check_layout(const Geo& g, long long slice, long long rowlen, int e, bool adjoint)
+// Independent element index of (slot s, x, y, z): blocked (R rows per block) or plain slices.
+struct Layout {
+    bool blocked;
+    long long S, pitch, ny, R;
+    long long index(int s, int x, int y, int z) const
+    {
+        const long long row = y + ny * z;
+        if (!blocked) return s * S + row * pitch + x;
+        return ((row / R) * 19 + s) * R * pitch + (row % R) * pitch + x;
+    }
+};
+
+// Every address a kernel forms for the cells of the sampled rows: own slot,
+// pull source (with the row's free-slip mirrors), the adjoint's outflow
+// copy one element further along x.
+static void check(const Geo& g, const Layout& L, int e, bool adjoint)
 {
-    const long long sb = slice * e, total = 19 * sb;
+    const long long total = 19 * L.S * e;
     std::vector<int> xs = {0, 1, 2, 31, 62, 63, 64, 65, g.nx / 2, g.nx - 3, g.nx - 2, g.nx - 1};
-    std::vector<int> ys = {0, 1, g.ny / 2, g.ny - 2, g.ny - 1};
+    std::vector<int> ys = {0, 1, 2, 7, 8, 15, 16, 31, 32, 33, g.ny / 2, g.ny - 2, g.ny - 1};
     std::vector<int> zs = {0, 1, g.nz / 2, g.nz - 2, g.nz - 1};
     for (int z : zs) for (int y : ys) {
         if (y < 0 || y >= g.ny || z < 0 || z >= g.nz) continue;
+        const long long row = y + (long long)g.ny * z;
         const int cls = row_class(g, y, z);
-        const StepOff O = step_offsets(slice, rowlen, g.ny, e, cls);
+        StepOff O;
+        long long rowbase;   // what the kernel adds to the array base before the lane offset
+        uint32_t off0;       // lane offset of x = 0
+        if (L.blocked) {
+            O = step_offsets_blocked(g.pitch, g.ny, g.lrb, e, cls, block_edge(g, row));
+            rowbase = row_start(g, row, e);
+            off0 = 0;
+        } else {
+            O = step_offsets(L.S, L.pitch, g.ny, e, cls);
+            rowbase = 0;
+            off0 = (uint32_t)(row * L.pitch) * (uint32_t)e;
+        }
         const int my = cls / 3, mz = cls % 3;
         for (int x : xs) {
             if (x < 0 || x >= g.nx) continue;
-            const long long cell = x + rowlen * (y + (long long)g.ny * z);
-            const uint32_t off = (uint32_t)cell * (uint32_t)e;   // the kernels' 32-bit lane offset
+            const uint32_t off = off0 + (uint32_t)x * (uint32_t)e;   // the kernels' 32-bit lane offset
             for (int I = 0; I < 19; I++) {
                 checked++;
-                // own slot
-                const long long own = O.lo[I] + (long long)(uint32_t)(off + O.oo[I]);
-                if (own != I * sb + cell * e) fail("own", g.nx, g.ny, g.nz, e, cls, x, y, z, I, own, I * sb + cell * e);
-                if (own < 0 || own + e > total) fail("own-bounds", g.nx, g.ny, g.nz, e, cls, x, y, z, I, own, total);
-                // pull source with the row's free-slip mirrors
+                const long long own = rowbase + O.lo[I] + (long long)(uint32_t)(off + O.oo[I]);
+                const long long own_want = L.index(I, x, y, z) * e;
+                if (own != own_want) fail("own", g, e, cls, x, y, z, I, own, own_want);
+                if (rowbase + O.even[I] + (long long)off != own_want && L.blocked) fail("own-even", g, e, cls, x, y, z, I, rowbase + O.even[I] + off, own_want);
+                if (own < 0 || own + e > total) fail("own-bounds", g, e, cls, x, y, z, I, own, total);
                 int cx = D[I][0], cy = D[I][1], cz = D[I][2];
                 int jx = cx, jy = cy, jz = cz;
                 if ((my == 1 && cy == 1) || (my == 2 && cy == -1)) { jy = -cy; cy = 0; }
@@ -83,15 +111,14 @@ static void check_layout(const Geo& g, long long slice, long long rowlen, int e,
                 const int sx = x - cx, sy = y - cy, sz = z - cz;
                 if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz) continue;
                 const int slot = opposite(find(jx, jy, jz));
-                const long long want = slot * sb + (sx + rowlen * (sy + (long long)g.ny * sz)) * e;
-                const long long nb = O.lo[I] + (long long)(uint32_t)(off + O.on[I]);
-                if (nb != want) fail("neighbour", g.nx, g.ny, g.nz, e, cls, x, y, z, I, nb, want);
-                if (O.odd[I] + (long long)off != want) fail("fast", g.nx, g.ny, g.nz, e, cls, x, y, z, I, O.odd[I] + off, want);
-                if (nb < 0 || nb + e > total) fail("neighbour-bounds", g.nx, g.ny, g.nz, e, cls, x, y, z, I, nb, total);
-                // the adjoint's outflow copy reads one element further along x
+                const long long want = L.index(slot, sx, sy, sz) * e;
+                const long long nb = rowbase + O.lo[I] + (long long)(uint32_t)(off + O.on[I]);
+                if (nb != want) fail("neighbour", g, e, cls, x, y, z, I, nb, want);
+                if (rowbase + O.odd[I] + (long long)off != want) fail("fast", g, e, cls, x, y, z, I, rowbase + O.odd[I] + off, want);
+                if (nb < 0 || nb + e > total) fail("neighbour-bounds", g, e, cls, x, y, z, I, nb, total);
                 if (adjoint && D[I][0] == 1 && x == g.nx - 1) {
-                    const long long cp = O.lo[I] + (long long)(uint32_t)(off + O.on[I] + (uint32_t)e);
-                    if (cp != want + e || cp + e > total) fail("adjoint-copy", g.nx, g.ny, g.nz, e, cls, x, y, z, I, cp, want + e);
+                    const long long cp = rowbase + O.lo[I] + (long long)(uint32_t)(off + O.on[I] + (uint32_t)e);
+                    if (cp != want + e || cp + e > total) fail("adjoint-copy", g, e, cls, x, y, z, I, cp, want + e);
                 }
             }
         }
@@ -109,28 +136,32 @@ int main()
         {800, 800, 128, {1, 2, 1, 2, 4, 3}},
         {256, 256, 96, {1, 2, 3, 3, 4, 3}},
         {37, 29, 23, {4, 4, 3, 3, 3, 3}},
-        {1024, 1024, 500, {1, 2, 3, 3, 4, 3}},   // free-slip faces: FP32 refused, binary16 near 1 GiB refused
-        {1024, 1024, 127, {1, 2, 3, 3, 4, 3}},   // free-slip faces, FP32 slices just below 512 MiB
-        {1024, 1024, 500, {1, 2, 1, 2, 4, 4}},   // no free-slip face: FP32 slices just below 2 GiB
+        {1024, 1024, 500, {1, 2, 3, 3, 4, 3}},   // free-slip faces: canonical FP32 refused for the push
+        {1024, 1024, 127, {1, 2, 3, 3, 4, 3}},   // free-slip faces, canonical FP32 slices just below 512 MiB
+        {1024, 1024, 500, {1, 2, 1, 2, 4, 4}},   // no free-slip face: canonical FP32 slices just below 2 GiB
+        {4096, 4096, 40, {1, 2, 3, 3, 4, 3}},    // in-place array 48 GiB in FP64
     };
     for (const Case& c : cases) {
         for (int e : {8, 4, 2}) {
             Geo g{};
             g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
             g.ncx = (g.nx + 63) / 64; g.pitch = g.ncx * 64; g.wpr = g.ncx;
+            g.lrb = 0;
+            while (g.lrb < 5 && g.ny % (2 << g.lrb) == 0) g.lrb++;
             for (int k = 0; k < 6; k++) g.face[k] = c.face[k];
             g.S = (long long)g.pitch * g.ny * g.nz;
             g.N = (long long)g.nx * g.ny * g.nz;
-            // the size rule of lbm_create / lbm_adjoint_step, restated: eight
-            // slices with a free-slip y or z face, else two, below 2^32 bytes
+            // the in-place array (row blocks): lbm_create's limit, restated
+            if ((19ll * g.pitch * g.ny + 40ll * 32 * g.pitch + 2ll * g.pitch) * e < (1ll << 32))
+                check(g, Layout{true, g.S, g.pitch, g.ny, 1ll << g.lrb}, e, false);
+            // canonical arrays of the push and adjoint: eight slices with a
+            // free-slip y or z face, else two, below 2^32 bytes
             bool freeslip = false;
             for (int k = 2; k < 6; k++) freeslip = freeslip || c.face[k] == 3;
             const long long span = freeslip ? 8 : 2;
-            if (span * g.S * e >= (1ll << 32)) continue;   // refused
-            check_layout(g, g.S, g.pitch, e, false);   // in-place array (odd step)
             if (span * g.N * e < (1ll << 32)) {
-                check_layout(g, g.N, g.nx, e, false);  // canonical arrays (push)
-                check_layout(g, g.N, g.nx, e, true);   // adjoint arrays
+                check(g, Layout{false, g.N, g.nx, g.ny, 1}, e, false);   // push
+                check(g, Layout{false, g.N, g.nx, g.ny, 1}, e, true);    // adjoint
             }
         }
     }
@@ -157,17 +188,17 @@ def test_slot_offsets_resolve_inside_the_array(tmp_path):
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="liblbm.so not built")
 def test_create_refuses_grids_beyond_32bit_offsets():
-    """A slice pair of 2 GiB or more is refused before any device call or
-    any read of the (here one-byte) solid mask."""
+    """A grid whose in-place offsets would not fit 32 bits (19 populations
+    of one xy plane reach 4 GiB) is refused before any device call or any read
+    of the (here one-byte) solid mask."""
     from paper_2607_04516_amd import binding
     lib = binding.load()
     p = binding._Params()
     p.tau0, p.c_smag, p.delta, p.rho0 = 0.6, 0.1, 1.0, 1.0
     p.storage = binding.F32
     solid = (ctypes.c_uint8 * 1)()
-    cases = [((1024, 1024, 512), (1, 2, 1, 2, 4, 4)),   # FP32 slice 2 GiB
-             ((1024, 1024, 200), (1, 2, 3, 3, 4, 3)),   # 839 MB with free-slip faces (limit 512 MiB)
-             ((1024, 1024, 130), (1, 2, 1, 2, 4, 3))]   # 545 MB, free-slip top
+    cases = [((8192, 8192, 3), (1, 2, 1, 2, 4, 4)),   # 19 populations of an xy plane: 5.1 GB in FP32
+             ((16384, 4096, 3), (1, 2, 3, 3, 4, 3))]
     for dims, faces in cases:
         for k in range(6):
             p.face[k] = faces[k]
