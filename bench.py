@@ -243,6 +243,11 @@ def copy_bandwidth():
     return best
 
 
+# the files that define the step kernels k_even / k_odd (the counter record
+# stays valid while these are unchanged)
+STEP_KERNEL_SOURCES = ("lbm_step.hip", "lbm_device.h", "lbm_launch.h", "lbm_general.h")
+
+
 def traffic_from_profiles(storage):
     """HBM bytes per step-kernel launch from the committed counter summary,
     if it was taken on the current kernel sources (else None)."""
@@ -253,12 +258,47 @@ def traffic_from_profiles(storage):
     rec = json.load(open(path))
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2607_04516_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in STEP_KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     if rec.get("sources_sha256") != h.hexdigest() or storage not in rec.get("per_launch_bytes", {}):
         return None, rec.get("sources_sha256")
     return rec["per_launch_bytes"][storage], rec.get("sources_sha256")
+
+
+def cpu_info():
+    """(CPU model name, cores this process may use, logical CPUs of the host)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, usable, os.cpu_count()
+
+
+def cpu_baseline_openmp(seconds=12.0, crop=(160, 160)):
+    """The same oracle source built with OpenMP over the step's z planes
+    (oracle variant "omp"), timed in a child process on the cores this
+    process may use (OMP_NUM_THREADS if set)."""
+    import subprocess
+    _, usable, _ = cpu_info()
+    env = dict(os.environ, LBM_ORACLE_VARIANT="omp")
+    env.setdefault("OMP_NUM_THREADS", str(usable))
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--cpu-omp-only", "--cpu-crop", str(crop[0]), str(crop[1]),
+           "--cpu-seconds", str(seconds)]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600, env=env)
+    if r.returncode != 0:
+        raise RuntimeError(f"OpenMP oracle child failed with status {r.returncode}")
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    rec["cores"] = int(env["OMP_NUM_THREADS"])
+    return rec
 
 
 def cpu_baseline(w, seconds=12.0, crop=(160, 160)):
@@ -285,9 +325,12 @@ def cpu_baseline(w, seconds=12.0, crop=(160, 160)):
         el = time.perf_counter() - t0
         if el >= seconds or steps >= 200:
             break
-    return {"value": fluid * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, 1 thread, {cx}x{cy}x{w.nz} crop of {w.name} "
-                      f"({fluid} fluid cells), {steps} steps in {el:.1f} s"}
+    threads = os.environ.get("OMP_NUM_THREADS", "1") if os.environ.get("LBM_ORACLE_VARIANT") == "omp" else "1"
+    model, usable, logical = cpu_info()
+    return {"value": fluid * steps / el / 1e6, "unit": "MLUPS", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 oracle, {threads} thread(s), {cx}x{cy}x{w.nz} crop of {w.name} "
+                      f"({fluid} fluid cells), {steps} steps in {el:.1f} s",
+            "cpu_model": model, "nproc": usable, "logical_cpus": logical}
 
 
 def main():
@@ -308,6 +351,10 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint-cost workload and print its record (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=1000, help="time steps T of the adjoint workload")
+    ap.add_argument("--cpu-omp-only", action="store_true",
+                    help="time only the OpenMP build of the oracle on a crop and print its record")
+    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(160, 160))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--nx", type=int, default=800)
     ap.add_argument("--ny", type=int, default=800)
     ap.add_argument("--nz", type=int, default=128)
@@ -317,6 +364,12 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU slab decomposition is a design, not a measured path)", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_omp_only:
+        from paper_2607_04516_amd import workloads
+        w = workloads.urban_km("f32", nx=args.nx, ny=args.ny, nz=args.nz)
+        print(json.dumps(cpu_baseline(w, args.cpu_seconds, tuple(args.cpu_crop))), flush=True)
+        return
 
     import torch
 
@@ -352,9 +405,11 @@ def main():
     if not args.no_extra:
         for s in ("f16s", "bf16s"):
             r = time_forward(w, s, args.steps, args.warmup)
+            tb, _ = traffic_from_profiles(s)
             extra[s] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
                         "kernel_ms": round(r["kernel_ms"], 4), "achieved_gbs": round(r["achieved_gbs"], 1),
                         "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        "traffic": None if tb is None else round(tb / (r["kernel_ms"] * 1e-3) / 1e9, 1),
                         "vs_f32_mlups": round(r["mlups"] / res["mlups"], 3)}
             print(f"[bench] {s}: {r['mlups']:.0f} MLUPS, {r['achieved_gbs']:.0f} GB/s", file=sys.stderr,
                   flush=True)
@@ -394,6 +449,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a crop", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w)
+        print("[bench] timing the OpenMP build of the oracle on a larger crop", file=sys.stderr, flush=True)
+        cpu["openmp"] = cpu_baseline_openmp()
 
     line = {
         "metric": METRIC,

@@ -19,21 +19,38 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "lbm_oracle.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# Builds of the same source: the plain one everything uses; "omp" splits the
+# step's z planes over OpenMP threads (only to time the oracle on all host
+# cores); "san" is instrumented with AddressSanitizer and UBSan (host code
+# checks; load it in a process started with libasan preloaded).  The build a
+# process loads is chosen by LBM_ORACLE_VARIANT ("", "omp" or "san").
+_VARIANTS = {
+    "": ([], "liboracle.so"),
+    "omp": (["-fopenmp"], "liboracle_omp.so"),
+    "san": (["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"],
+            "liboracle_san.so"),
+}
+_LIB = os.path.join(_HERE, _VARIANTS[""][1])
+
+
+def _lib_path(variant: str) -> str:
+    return os.path.join(_HERE, _VARIANTS[variant][1])
 
 PERIODIC, INFLOW_EQ, OUTFLOW_ZG, FREESLIP, WALL = 0, 1, 2, 3, 4
 NQ = 19
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, variant: str = "") -> str:
     """Compile the oracle with gcc (strict IEEE: no contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
+    flags, _ = _VARIANTS[variant]
+    out = _lib_path(variant)
+    if force or not os.path.exists(out):
         srcs = [s for s in _SRC if os.path.exists(s)]
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-o", _LIB + ".tmp", *srcs, "-lm"]
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", *flags, "-fPIC", "-shared",
+               "-o", out + ".tmp", *srcs, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class _Cfg(ctypes.Structure):
@@ -72,9 +89,11 @@ def face_value(inflow, face, x, y, z, nz):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        variant = os.environ.get("LBM_ORACLE_VARIANT", "")
+        path = _lib_path(variant)
+        if not os.path.exists(path):
+            build(force=True, variant=variant)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.or_lattice.argtypes = [P, P, P]
         lib.or_equilibrium.argtypes = [ctypes.c_double, P, P]

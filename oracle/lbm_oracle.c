@@ -433,7 +433,9 @@ int or_step(const or_cfg *g, const uint8_t *solid, const double *inflow,
     g_err = check_cfg(g);
     if (g_err) return g_err;
     int64_t N = (int64_t)g->nx * g->ny * g->nz;
-    /* 1. collision */
+    /* 1. collision (z planes are independent: the OpenMP build of the
+     * oracle, used only to time it on all host cores, splits them) */
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < g->nz; z++)
         for (int y = 0; y < g->ny; y++)
             for (int x = 0; x < g->nx; x++) {
@@ -456,6 +458,7 @@ int or_step(const or_cfg *g, const uint8_t *solid, const double *inflow,
                 for (int i = 0; i < NQ; i++) fs[i * N + n] = fo[i];
             }
     /* 2. streaming */
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < g->nz; z++)
         for (int y = 0; y < g->ny; y++)
             for (int x = 0; x < g->nx; x++) {

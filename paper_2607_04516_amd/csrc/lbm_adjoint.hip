@@ -450,7 +450,10 @@ __device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__
     }
     if (!solid_lane) {
 #pragma unroll
-        for (int i = 0; i < NQ; i++) h[i] = C::dec(f_t[(long long)i * g.N + cell]);
+        // f(t) is read once and lam(t) written once per step: streaming
+        // (non-temporal) hints, 286 -> 266 us per step on the 256x256x96
+        // grid (either alone gains half of that)
+        for (int i = 0; i < NQ; i++) h[i] = C::dec(__builtin_nontemporal_load(f_t + (long long)i * g.N + cell));
     } else {
 #pragma unroll
         for (int i = 0; i < NQ; i++) h[i] = R(0);
@@ -458,7 +461,7 @@ __device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__
     collision_transpose<R>(h, ls, P);
     if (chunk_has_probe(pr, wave) && !solid_lane) add_probe_sources<R>(pr, cell, cell - lane, h, P, ls);
 #pragma unroll
-    for (int j = 0; j < NQ; j++) lam[(long long)j * g.N + cell] = solid_lane ? R(0) : ls[j];
+    for (int j = 0; j < NQ; j++) __builtin_nontemporal_store(solid_lane ? R(0) : ls[j], lam + (long long)j * g.N + cell);
 }
 
 // dL/du_in(face F, height z): the sum over the face's inflow cells at that

@@ -178,11 +178,15 @@ def test_slot_offsets_resolve_inside_the_array(tmp_path):
     src.write_text(SRC)
     exe = tmp_path / "offsets"
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    subprocess.check_call([hipcc, "-O1", "-std=c++17", "--offload-arch=gfx950", "-I", INC, "-I", CSRC, str(src),
-                           "-o", str(exe)], stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
-    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600)
+    # host code built with AddressSanitizer and UBSan (device code untouched)
+    subprocess.check_call([hipcc, "-O1", "-std=c++17", "--offload-arch=gfx950", "-I", INC, "-I", CSRC,
+                           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                           "-Xarch_host", "-fno-sanitize-recover=undefined", str(src), "-o", str(exe)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
     print(r.stdout)
-    assert r.returncode == 0, r.stdout
+    assert r.returncode == 0, r.stdout + r.stderr[-2000:]
     assert "0 errors" in r.stdout
 
 
