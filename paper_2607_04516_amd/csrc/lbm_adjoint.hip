@@ -467,8 +467,9 @@ __device__ inline void adjoint_wave(const typename Codec<K>::store* __restrict__
 // dL/du_in(face F, height z): the sum over the face's inflow cells at that
 // height of lam*_k d feq_k/du at each cell's own inflow velocity (the
 // derivative with respect to a shift of the whole row).  One block per
-// (F, z), a fixed-order tree over the cells, then a compensated (Neumaier)
-// update of g[0] (sum) and g[1] (compensation).
+// (F, z): wavefront reductions over the cells and the block's waves in
+// order, then a compensated (Neumaier) update of g[0] (sum) and g[1]
+// (compensation).
 constexpr int ADJ_RED = 256;
 
 template <int K>
@@ -504,18 +505,18 @@ __device__ inline void adjoint_inflow(const typename Codec<K>::real* __restrict_
             acc[2] += wl * (R(3) * R(c.z) + R(9) * e * R(c.z) - R(3) * uz);
         });
     }
-    __shared__ R sh[3][ADJ_RED];
-    for (int k = 0; k < 3; k++) sh[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = ADJ_RED / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int k = 0; k < 3; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-        __syncthreads();
+    constexpr int NW = ADJ_RED / 64;
+    __shared__ R sh[3][NW];
+    for (int k = 0; k < 3; k++) {
+        const R w = wave_sum(acc[k]);
+        if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = w;
     }
+    __syncthreads();
     if (threadIdx.x < 3 && count > 0) {
         const long long o = ((long long)F * g.nz + zz) * 3 + threadIdx.x;
         const long long o2 = 6ll * g.nz * 3 + o;
-        const R xv = sh[threadIdx.x][0];
+        R xv = sh[threadIdx.x][0];
+        for (int w = 1; w < NW; w++) xv += sh[threadIdx.x][w];
         const R s = gacc[o];
         const R tsum = s + xv;
         R comp = gacc[o2];
@@ -586,7 +587,7 @@ static hipError_t adjoint_k(const DevCtx& d, const void* f_t, const void* lam_ne
     // for four.  FP64 needs registers for fewer than four anyway.
     size_t lds = 0;
     if (K != 0 && d.lds_per_cu > 0) {
-        const size_t stat = 3 * ADJ_RED * sizeof(R);   // the inflow blocks' reduction buffer
+        const size_t stat = 3 * (ADJ_RED / 64) * sizeof(R);   // the inflow blocks' reduction buffer
         const size_t quarter = (size_t)d.lds_per_cu / 4 / 1024 * 1024;
         if (quarter > stat + 1024) lds = quarter - stat;
     }

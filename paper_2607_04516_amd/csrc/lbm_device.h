@@ -788,6 +788,44 @@ __device__ inline uint64_t solid_src_mask(const RowWin& W)
     else return wc;
 }
 
+// Wavefront reductions: an xor butterfly over 32, 16, ..., 1 lanes of the
+// 64-lane wave (cross-lane permutes, no LDS array, no barrier).  The pairing
+// is fixed and a + b == b + a exactly, so every lane ends with the same
+// value and the result is the same on every run.
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// Sum over a block of B = 64 k threads: wave sums, then the k wave results in
+// wave order; every thread gets the result.  sh: k + 1 doubles of LDS.
+template <int B>
+__device__ inline double block_sum_waves(double v, double* sh)
+{
+    static_assert(B % 64 == 0, "whole waves");
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int k = 1; k < B / 64; k++) t += sh[k];
+        sh[B / 64] = t;
+    }
+    __syncthreads();
+    const double r = sh[B / 64];
+    __syncthreads();   // sh may be reused by the caller
+    return r;
+}
+
 // splitmix64 (Steele, Lea & Flood 2014): golden-gamma increment, then the
 // published finaliser.
 __host__ __device__ inline uint64_t splitmix64(uint64_t x)

@@ -409,7 +409,8 @@ __global__ void k_probe_cells(const typename Codec<K>::store* f, const uint64_t*
 // Mass / energy / watchdog reduction over fluid, non-inflow cells.
 // Pass 1: per lane a Neumaier-compensated sum of rho - rho0 in the real
 // type and double sums of the kinetic energy, plus max |u|^2, max |rho-rho0|
-// and a non-finite flag; then a fixed-order double tree over the block.
+// and a non-finite flag; then wavefront reductions (xor butterflies) and the
+// block's four wave results in order, all in double.
 // Pass 2: one block reduces the block partials in a fixed order.
 // --------------------------------------------------------------------------
 constexpr int RED_THREADS = 256;
@@ -447,30 +448,28 @@ k_mass_partial(const typename Codec<K>::store* f, const uint64_t* __restrict__ m
         umax = fmax(umax, u2);
         dmax = fmax(dmax, fabs((double)drho));
     }
-    __shared__ double sh[5][RED_THREADS];
-    sh[0][threadIdx.x] = (double)s + (double)comp;
-    sh[1][threadIdx.x] = e;
-    sh[2][threadIdx.x] = umax;
-    sh[3][threadIdx.x] = dmax;
-    sh[4][threadIdx.x] = bad;
+    // wavefront reductions, then the block's waves in order
+    constexpr int NW = RED_THREADS / 64;
+    __shared__ double sh[5][NW];
+    const double r[5] = {wave_sum((double)s + (double)comp), wave_sum(e), wave_max(umax), wave_max(dmax),
+                         wave_max(bad)};
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 5; k++) sh[k][threadIdx.x >> 6] = r[k];
     __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
-            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
-            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + w]);
-            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + w]);
-            sh[4][threadIdx.x] = fmax(sh[4][threadIdx.x], sh[4][threadIdx.x + w]);
+    if (threadIdx.x == 0) {
+        double a[5] = {sh[0][0], sh[1][0], sh[2][0], sh[3][0], sh[4][0]};
+        for (int w = 1; w < NW; w++) {
+            a[0] += sh[0][w];
+            a[1] += sh[1][w];
+            for (int k = 2; k < 5; k++) a[k] = fmax(a[k], sh[k][w]);
         }
-        __syncthreads();
+        for (int k = 0; k < 5; k++) partial[5 * blockIdx.x + k] = a[k];
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 5; k++) partial[5 * blockIdx.x + k] = sh[k][0];
 }
 
 __global__ void __launch_bounds__(RED_THREADS) k_mass_final(const double* partial, int nb, double* out)
 {
-    __shared__ double sh[5][RED_THREADS];
+    __shared__ double sh[5][RED_THREADS / 64];
     double a[5] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += RED_THREADS) {
         a[0] += partial[5 * b];
@@ -479,18 +478,20 @@ __global__ void __launch_bounds__(RED_THREADS) k_mass_final(const double* partia
         a[3] = fmax(a[3], partial[5 * b + 3]);
         a[4] = fmax(a[4], partial[5 * b + 4]);
     }
-    for (int k = 0; k < 5; k++) sh[k][threadIdx.x] = a[k];
+    const double r[5] = {wave_sum(a[0]), wave_sum(a[1]), wave_max(a[2]), wave_max(a[3]), wave_max(a[4])};
+    constexpr int NW = RED_THREADS / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 5; k++) sh[k][threadIdx.x >> 6] = r[k];
     __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
-            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
-            for (int k = 2; k < 5; k++) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + w]);
+    if (threadIdx.x == 0) {
+        double t[5] = {sh[0][0], sh[1][0], sh[2][0], sh[3][0], sh[4][0]};
+        for (int w = 1; w < NW; w++) {
+            t[0] += sh[0][w];
+            t[1] += sh[1][w];
+            for (int k = 2; k < 5; k++) t[k] = fmax(t[k], sh[k][w]);
         }
-        __syncthreads();
+        for (int k = 0; k < 5; k++) out[k] = t[k];
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 5; k++) out[k] = sh[k][0];
 }
 
 // Wave-mask table, built once per grid: the solid-source masks of every wave

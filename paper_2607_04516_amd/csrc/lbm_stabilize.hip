@@ -4,7 +4,8 @@
 // least-squares smallest correction that zeroes the flux.
 //
 // Two launches, no host round trip: a fixed grid of FLUX_BLOCKS blocks writes
-// one partial sum each (grid-stride over the cells, tree in LDS); every block
+// one partial sum each (grid-stride over the cells, wavefront reductions);
+// every block
 // of the shift kernel sums the partials in the same fixed order, so all of
 // them see the same Phi, and shifts its cells.  Deterministic run to run.
 #include "lbm_launch.h"
@@ -23,30 +24,17 @@ __device__ inline double flux_of(const double* __restrict__ uin, int slot, int F
     return (F & 1) ? v : -v;
 }
 
-__device__ inline double block_sum(double v, double* red)
-{
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int w = FLUX_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    const double s = red[0];
-    __syncthreads();
-    return s;
-}
 
 __global__ void __launch_bounds__(FLUX_THREADS)
 k_flux_partial(const int* __restrict__ slot, const int* __restrict__ face, long long n,
                const double* __restrict__ uin, double* __restrict__ partial)
 {
-    __shared__ double red[FLUX_THREADS];
+    __shared__ double red[FLUX_THREADS / 64 + 1];
     double acc = 0.0;
     for (long long i = blockIdx.x * (long long)FLUX_THREADS + threadIdx.x; i < n;
          i += (long long)FLUX_THREADS * FLUX_BLOCKS)
         acc += flux_of(uin, slot[i], face[i]);
-    const double s = block_sum(acc, red);
+    const double s = block_sum_waves<FLUX_THREADS>(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
@@ -54,8 +42,8 @@ __global__ void __launch_bounds__(FLUX_THREADS)
 k_flux_shift(const int* __restrict__ slot, const int* __restrict__ face, long long n, double* __restrict__ uin,
              const double* __restrict__ partial, double* __restrict__ phi_out, int apply)
 {
-    __shared__ double red[FLUX_THREADS];
-    const double phi = block_sum(threadIdx.x < FLUX_BLOCKS ? partial[threadIdx.x] : 0.0, red);
+    __shared__ double red[FLUX_THREADS / 64 + 1];
+    const double phi = block_sum_waves<FLUX_THREADS>(threadIdx.x < FLUX_BLOCKS ? partial[threadIdx.x] : 0.0, red);
     if (blockIdx.x == 0 && threadIdx.x == 0 && phi_out) phi_out[0] = phi;
     if (!apply) return;
     const double delta = phi / (double)n;
