@@ -91,12 +91,15 @@ typedef struct {
  * (buildings and terrain voxels, Sec. 2.1); copied and bit-packed on the
  * device.  Allocates the population array (19 * nx_pitch * ny * nz * sizeof(store))
  * and initialises the state at t = 0 to feq(rho0, u_init + noise) in fluid
- * cells and h = 0 in solid cells.  Size limit: one population slice
- * (nx_pitch * ny * nz * sizeof(store), nx_pitch = nx rounded up to 64) must
- * stay below 2 GiB, or below 512 MiB when a y or z face is LBM_FREESLIP or
- * LBM_HALO (the kernels' 32-bit slot offsets span up to eight slices there);
- * larger grids return EINVAL.  Errors: EINVAL, ENOMEM, EHIP; *out is NULL on
- * error and lbm_last_error(NULL) gives the message. */
+ * cells and h = 0 in solid cells.  The array is laid out in row blocks
+ * (R consecutive rows (y, z) keep their 19 populations together, R the
+ * largest power of two <= 32 dividing ny), so the step kernels' 32-bit slot
+ * offsets span one xy plane of all 19 populations: size limit
+ * (19 * nx_pitch * ny + 1282 * nx_pitch) * sizeof(store) < 4 GiB,
+ * nx_pitch = nx rounded up to 64; larger grids return EINVAL.
+ * lbm_push_step and lbm_adjoint_step have a tighter limit (below).  Errors:
+ * EINVAL, ENOMEM, EHIP; *out is NULL on error and lbm_last_error(NULL) gives
+ * the message. */
 int lbm_create(const lbm_grid *grid, const uint8_t *solid, const lbm_params *params, lbm_ctx **out);
 
 /* Set the velocity profile of an INFLOW_EQ face: host double [nz][3]; every
@@ -312,7 +315,10 @@ int lbm_set_stats(lbm_ctx *ctx, void *acc, int32_t stride);
 /* One step from a canonical state to a canonical state, out of place:
  * src, dst device store [19][N], distinct.  Uses the context's geometry,
  * parameters and inflow boundary states; does not touch its state or time.
- * This is the recompute step of the checkpointed adjoint. */
+ * This is the recompute step of the checkpointed adjoint.  Size limit (the
+ * kernel's 32-bit slot offsets span up to two population slices, or eight
+ * when a y or z face is LBM_FREESLIP): nx * ny * nz *
+ * sizeof(store) below 2 GiB, or below 512 MiB with such faces; else EINVAL. */
 int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
 
 /* One discrete-adjoint step (transpose of the linearised update, eqs. D.2-D.4
@@ -328,7 +334,9 @@ int lbm_push_step(lbm_ctx *ctx, const void *src, void *dst);
  * of the derivative with respect to their own velocity, i.e. with respect to
  * a uniform shift of that row), as a compensated (Neumaier) sum with [1] the
  * compensation.  Solid and inflow cells get lam = 0.  One kernel launch on
- * the context's stream. */
+ * the context's stream.  Size limit as for lbm_push_step, with the real
+ * type's size (nx * ny * nz * sizeof(real) below 2 GiB, or 512 MiB with
+ * free-slip y/z faces); else EINVAL. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_t, const void *lam_next, void *lam,
                      const void *probe_src, void *g_inflow);
 
