@@ -77,6 +77,25 @@ __device__ inline void st_stream(T* p, T v)
 {
     __builtin_nontemporal_store(v, p);
 }
+// Odd-step access of direction I: the slots of directions with c_x = 0 are
+// read and written at the wave's own 64-cell x range (whole lines that no
+// other wave touches) and take non-temporal hints at every storage width;
+// the x-shifted ones share their chunk-edge lines with the neighbouring
+// wave and stay plain.  On the 800x800x128 grid: FP32 odd 2509 -> 2356 us,
+// binary16 1431 -> 1375 us (loads and stores both hinted; either alone, or
+// stores hinted in every direction, is slower).
+template <int I, typename T>
+__device__ inline T ld_odd(const T* p)
+{
+    if constexpr (dirv(I).x == 0) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <int I, typename T>
+__device__ inline void st_odd(T* p, T v)
+{
+    if constexpr (dirv(I).x == 0) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 template <typename R>
 __device__ inline void inflow_eq_stored(const double* __restrict__ uin, const Geo& g, int face, int x, int y, int z,
@@ -224,13 +243,13 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
         // fast path: no solid neighbour, no face lane
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            h[I] = C::raw(ld_pop((const T*)(base + O.odd[I] + off)));
+            h[I] = C::raw(ld_odd<I>((const T*)(base + O.odd[I] + off)));
         });
         R drho, ux, uy, uz, tau;
         collide_at<R, C::SC>(h, P, g, x, y, z, drho, ux, uy, uz, tau);
         sfor<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            st_pop((T*)(base + O.odd[I] + off), C::pack(h[opp(I)]));
+            st_odd<I>((T*)(base + O.odd[I] + off), C::pack(h[opp(I)]));
         });
         if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
         return;
@@ -249,7 +268,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
     });
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        h[I] = C::raw(ld_pop((const T*)(base + O.lo[I] + so[I])));
+        h[I] = C::raw(ld_odd<I>((const T*)(base + O.lo[I] + so[I])));
     });
     const bool inflow_lane = x_lo && g.face[0] == F_INFLOW && lane == 0;
     const bool outflow_lane = x_hi && g.face[1] == F_OUTFLOW && lane == l_out;
@@ -276,7 +295,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
     }
     sfor<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        st_pop((T*)(base + O.lo[I] + so[I]), C::pack(h[opp(I)]));
+        st_odd<I>((T*)(base + O.lo[I] + so[I]), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
 }
