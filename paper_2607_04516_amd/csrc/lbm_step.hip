@@ -45,17 +45,18 @@ __device__ inline long long xcd_remap(long long nblocks_padded)
     return blockIdx.x;
 }
 
-// Population traffic of the step kernels.  The odd step and the push use
-// plain loads and stores: their pulls share the lines at chunk edges with
-// the neighbouring waves, and the streaming (non-temporal) hint made the
-// odd step 19% slower.  The even step touches each line once: with the
-// row-block layout, non-temporal loads and stores took the FP32 even step
-// from 2.54 to 2.13 ms on the kilometre grid; 16-bit storage is fastest with
-// non-temporal stores only (1.16 ms, against 1.20 with both).  On the
-// 256x256x96 adjoint grid (0.48 GB, twice the last-level cache) the hint
-// still pays: the even step 196 -> 185 us, and the odd step that follows
-// 188 -> 151 us.  The push recompute is slower with it on either its loads
-// (215 -> 229 us) or its scattered stores (281 us).
+// Population traffic of the step kernels.  The even step touches each line
+// once: with the row-block layout, non-temporal (streaming) loads and stores
+// took the FP32 even step from 2.54 to 2.13 ms on the kilometre grid; 16-bit
+// storage is fastest with non-temporal stores only (1.16 ms, against 1.20
+// with both).  On the 256x256x96 adjoint grid (0.48 GB, twice the
+// last-level cache) the hint still pays: the even step 196 -> 185 us, and
+// the odd step that follows 188 -> 151 us.  The odd step's x-shifted pulls
+// share the lines at chunk edges with the neighbouring waves and stay plain
+// (the hint on every direction made the odd step 19% slower); its
+// directions with c_x = 0 take it (ld_odd / st_odd).  The push recompute is
+// slower with the hint on its loads (215 -> 229 us), on all its scattered
+// stores (281 us) or on its stores with c_x = 0 (221 us).
 template <typename T>
 __device__ inline T ld_pop(const T* p)
 {
