@@ -24,6 +24,17 @@ struct AdjProbes {
     const void* src;    // per call: [np][3] dL/du at the probes, or nullptr
 };
 
+// The same table for the forward step kernels, which add u of the state a
+// step starts from to the probes' compensated sums acc [2][np][3] (real
+// type of the codec).
+struct StepProbes {
+    const uint32_t* bits;
+    const unsigned* cell;
+    const int* id;
+    int n;
+    void* acc;
+};
+
 // Everything a kernel launch needs to know about one context.
 struct DevCtx {
     Geo g;
@@ -208,7 +219,9 @@ __host__ __device__ inline bool odd_wave_is_general(const Geo& g, int cx, int y,
     return false;
 }
 
-hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s);
+// probe_acc: NULL, or the accumulator the step kernels add the probe
+// velocities of the state at the step's start to (not together with stats).
+hipError_t launch_step(const DevCtx& d, int odd, void* stats, void* probe_acc, hipStream_t s);
 hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s);
 hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s);
 hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s);

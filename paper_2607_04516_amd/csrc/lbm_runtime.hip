@@ -59,7 +59,8 @@ struct lbm_ctx {
     double* u0 = nullptr;   // device [nz][3] scratch for initialisation
     int* probes = nullptr;  // device [np][3]
     int np = 0;
-    void* probe_tab = nullptr;  // device: adjoint probe table (chunk bits, sorted cells, probe ids)
+    void* probe_tab = nullptr;  // device: probe table (chunk bits, sorted cells, probe ids)
+    bool probe_fold = false;    // every probe is sampled by the fast step kernels (see lbm_set_probes)
     double* red_partial = nullptr;
     double* red_out = nullptr;  // device [5]
     unsigned* odd_list = nullptr;
@@ -852,25 +853,31 @@ static int mark(lbm_ctx* c)
     return LBM_OK;
 }
 
-static int one_step(lbm_ctx* c)
+static bool stats_due(const lbm_ctx* c)
 {
-    void* st = nullptr;
+    return c->stats && c->stats_stride > 0 && (c->t % c->stats_stride) == 0;
+}
+
+// One step t -> t+1.  probe_acc: NULL, or the probe accumulator to which the
+// step kernels add u(t) of the probe cells (never together with stats).
+static int one_step(lbm_ctx* c, void* probe_acc)
+{
+    void* st = stats_due(c) ? c->stats : nullptr;
     int rc;
-    if (c->stats && c->stats_stride > 0 && (c->t % c->stats_stride) == 0) st = c->stats;
     HIPCHK(c, vk_apply(c->vk, c->uin, c->t, c->stream), "synthetic inflow");
     if (c->flux_mode == 2)
         HIPCHK(c, launch_flux_balance(c->flux_cells, c->flux_cells + c->n_flux, c->n_flux, c->uin, c->flux_red,
                                       c->flux_red + flux_partial_count(), 1, c->stream), "flux balance");
     if (c->phase == 0) {
         if ((rc = mark(c)) != LBM_OK) return rc;
-        HIPCHK(c, launch_step(c->d, 0, st, c->stream), "even step");
+        HIPCHK(c, launch_step(c->d, 0, st, probe_acc, c->stream), "even step");
         if ((rc = mark(c)) != LBM_OK) return rc;
         c->phase = 1;
     } else {
         const bool out = has_outflow(c);
         if (out) HIPCHK(c, launch_outflow_ghost(c->d, c->stream), "outflow ghost");
         if ((rc = mark(c)) != LBM_OK) return rc;
-        HIPCHK(c, launch_step(c->d, 1, st, c->stream), "odd step");
+        HIPCHK(c, launch_step(c->d, 1, st, probe_acc, c->stream), "odd step");
         if ((rc = mark(c)) != LBM_OK) return rc;
         if (out) HIPCHK(c, launch_outflow_copy(c->d, c->f, 0, c->stream), "outflow copy");
         c->phase = 0;
@@ -909,11 +916,28 @@ static int step_n(lbm_ctx* c, int64_t n, void* acc)
     int rc = check_ready(c);
     if (rc != LBM_OK) return rc;
     const int wd = c->p.watchdog_stride;
+    // The sample u(t+1) after step t is taken by the kernels of step t+1,
+    // which form that velocity anyway (when lbm_set_probes found every probe
+    // in their reach and that step collects no statistics); samples that no
+    // step kernel takes (after the last step, before a watchdog check) go
+    // through the probe kernel.  Both give the same bits.
+    bool pending = false;   // u of the current state still to be added to acc
     for (int64_t k = 0; k < n; k++) {
-        if ((rc = one_step(c)) != LBM_OK) return rc;
-        if (acc) HIPCHK(c, launch_probe_cells(c->d, c->phase, c->probes, c->np, acc, c->stream), "probe accumulate");
-        if (wd > 0 && (c->t % wd) == 0 && (rc = watchdog(c)) != LBM_OK) return rc;
+        void* fold = nullptr;
+        if (pending) {
+            if (c->probe_fold && !stats_due(c)) fold = acc;
+            else HIPCHK(c, launch_probe_cells(c->d, c->phase, c->probes, c->np, acc, c->stream), "probe accumulate");
+            pending = false;
+        }
+        if ((rc = one_step(c, fold)) != LBM_OK) return rc;
+        pending = acc != nullptr;
+        if (wd > 0 && (c->t % wd) == 0) {
+            if (pending) HIPCHK(c, launch_probe_cells(c->d, c->phase, c->probes, c->np, acc, c->stream), "probe accumulate");
+            pending = false;
+            if ((rc = watchdog(c)) != LBM_OK) return rc;
+        }
     }
+    if (pending) HIPCHK(c, launch_probe_cells(c->d, c->phase, c->probes, c->np, acc, c->stream), "probe accumulate");
     return LBM_OK;
 }
 
@@ -1030,6 +1054,7 @@ int lbm_set_probes(lbm_ctx* c, const int32_t* cells, int32_t np)
         c->probe_tab = nullptr;
     }
     c->np = 0;
+    c->probe_fold = false;
     c->d.probes = AdjProbes{nullptr, nullptr, nullptr, 0, nullptr};
     if (np == 0) return LBM_OK;
     int rc = device_alloc(c, (void**)&c->probes, (size_t)np * 3 * sizeof(int), "probes");
@@ -1064,6 +1089,17 @@ int lbm_set_probes(lbm_ctx* c, const int32_t* cells, int32_t np)
     c->d.probes = AdjProbes{(const uint32_t*)tb, (const unsigned*)(tb + nwords * 4),
                             (const int*)(tb + nwords * 4 + (size_t)np * 4), np, nullptr};
     c->np = np;
+    // The step kernels can take the probe samples when every probe cell is a
+    // fluid, non-inflow cell off the x faces whose odd-step wave the fast
+    // kernel runs (not the general per-cell path); the even kernel runs all.
+    bool fold = true;
+    for (int p = 0; p < np && fold; p++) {
+        const int x = cells[3 * p], y = cells[3 * p + 1], z = cells[3 * p + 2];
+        const bool solid = (c->bits_host[((size_t)y + (size_t)g.ny * z) * g.wpr + (x >> 6)] >> (x & 63)) & 1ull;
+        fold = !solid && inflow_face_of(g, x, y, z) < 0 && x >= 1 && x <= g.nx - 2 &&
+               !odd_wave_is_general(g, x >> 6, y, z);
+    }
+    c->probe_fold = fold;
     return LBM_OK;
 }
 

@@ -120,13 +120,52 @@ __device__ inline void add_stats(R* stats, const Geo& g, int x, int y, int z, R 
     stats[5 * g.N + n] += uz * uz;
 }
 
+// Probe sampling inside the step: a lane whose cell is a registered probe
+// adds the velocity of the state the step starts from (the moments the
+// collision formed, before any nudging) to each of its probes' Neumaier
+// sums, in the arithmetic of the separate probe kernel.  Only waves whose
+// chunk bit is set search the sorted table; a probe's sums are written by
+// the one lane holding its cell.
+__device__ inline bool step_chunk_has_probe(const StepProbes& pr, long long wave)
+{
+    return ((pr.bits[wave >> 5] >> (wave & 31)) & 1u) != 0;
+}
+
+template <typename R>
+__device__ inline void step_probe_add(const StepProbes& pr, long long cell, long long cell0, R ux, R uy, R uz)
+{
+    int lo = 0, hi = pr.n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)pr.cell[mid] < cell0) lo = mid + 1;
+        else hi = mid;
+    }
+    R* acc = (R*)pr.acc;
+    auto add = [](R* sum, R* cmp, R xa) {
+        const R sa = *sum;
+        const R t = sa + xa;
+        *cmp += fabs(sa) >= fabs(xa) ? (sa - t) + xa : (xa - t) + sa;
+        *sum = t;
+    };
+    for (int e = lo; e < pr.n && (long long)pr.cell[e] < cell0 + 64; e++) {
+        if ((long long)pr.cell[e] != cell) continue;
+        const int p = pr.id[e];
+        R* sum = acc + 3 * p;
+        R* cmp = acc + 3 * (long long)pr.n + 3 * p;
+        add(sum, cmp, ux);
+        add(sum + 1, cmp + 1, uy);
+        add(sum + 2, cmp + 2, uz);
+    }
+}
+
 // ---------------------------------------------------------------- even step
 // FP32 without statistics: eight waves per SIMD (the SGPR count otherwise
 // limits the kernel to seven), 5% faster; the 16-bit forms are slower so.
-template <int K, bool STATS>
-__global__ void __launch_bounds__(256, (K == 1 && !STATS) ? 8 : 1)
+template <int K, bool STATS, bool PROBES>
+__global__ void __launch_bounds__(256, (K == 1 && !STATS && !PROBES) ? 8 : 1)
 k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin, Geo g,
-       Phys<typename Codec<K>::real> P, StepOff O, typename Codec<K>::real* stats, long long nwaves, long long nbp)
+       Phys<typename Codec<K>::real> P, StepOff O, typename Codec<K>::real* stats, StepProbes pr, long long nwaves,
+       long long nbp)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -168,6 +207,8 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
         st_stream((T*)(base + O.even[I] + off), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+    if constexpr (PROBES)
+        if (step_chunk_has_probe(pr, wave)) step_probe_add<R>(pr, x + (long long)g.nx * row, (long long)g.nx * row + cx * 64, ux, uy, uz);
 }
 
 // Waves the odd kernel below leaves to the general kernel (same test on
@@ -178,12 +219,13 @@ __device__ inline bool odd_general_wave(const Geo& g, int cx, int y, int z)
 }
 
 // ---------------------------------------------------------------- odd step
-template <int K, bool STATS>
+template <int K, bool STATS, bool PROBES>
 __global__ void __launch_bounds__(256)
 k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int* __restrict__ wave_idx,
       const uint64_t* __restrict__ wave_tab, const double* __restrict__ uin,
       const typename Codec<K>::store* __restrict__ ghost, Geo g, Phys<typename Codec<K>::real> P,
-      const StepOff* __restrict__ otab, typename Codec<K>::real* stats, long long nwaves, long long nbp)
+      const StepOff* __restrict__ otab, typename Codec<K>::real* stats, StepProbes pr, long long nwaves,
+      long long nbp)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -253,6 +295,8 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
             st_odd<I>((T*)(base + O.odd[I] + off), C::pack(h[opp(I)]));
         });
         if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+        if constexpr (PROBES)
+            if (step_chunk_has_probe(pr, wave)) step_probe_add<R>(pr, x + (long long)g.nx * row, (long long)g.nx * row + cx * 64, ux, uy, uz);
         return;
     }
 
@@ -299,6 +343,9 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
         st_odd<I>((T*)(base + O.lo[I] + so[I]), C::pack(h[opp(I)]));
     });
     if constexpr (STATS) add_stats<R>(stats, g, x, y, z, ux, uy, uz);
+    // (the runtime registers no x-face cell as a probe sampled here)
+    if constexpr (PROBES)
+        if (step_chunk_has_probe(pr, wave)) step_probe_add<R>(pr, x + (long long)g.nx * row, (long long)g.nx * row + cx * 64, ux, uy, uz);
 }
 
 // ---------------------------------------------------------------- push step
@@ -516,8 +563,8 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
 }
 
 
-template <int K>
-static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_t s)
+template <int K, bool STATS, bool PROBES>
+static hipError_t launch_fused_k(const DevCtx& d, int odd, void* stats, const StepProbes& pr, hipStream_t s)
 {
     using C = Codec<K>;
     using R = typename C::real;
@@ -525,27 +572,29 @@ static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, hipStream_
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
     const Phys<R> P = phys_of<K>(d);
-    const StepOff O = step_offsets_blocked(d.g.pitch, d.g.ny, d.g.lrb, (int)sizeof(typename C::store), 0, 0);
     auto* f = (typename C::store*)d.f;
     if (!odd) {
-        if (stats)
-            hipLaunchKernelGGL((k_even<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P, O,
-                               (R*)stats, nwaves, nbp);
-        else
-            hipLaunchKernelGGL((k_even<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P, O,
-                               (R*)stats, nwaves, nbp);
+        const StepOff O = step_offsets_blocked(d.g.pitch, d.g.ny, d.g.lrb, (int)sizeof(typename C::store), 0, 0);
+        hipLaunchKernelGGL((k_even<K, STATS, PROBES>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P,
+                           O, (R*)stats, pr, nwaves, nbp);
         return hipGetLastError();
     }
-    const auto* gh = (const typename C::store*)d.ghost;
-    if (stats)
-        hipLaunchKernelGGL((k_odd<K, true>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx, d.wave_tab,
-                           d.uin, gh, d.g, P, d.off_odd, (R*)stats, nwaves, nbp);
-    else
-        hipLaunchKernelGGL((k_odd<K, false>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx, d.wave_tab,
-                           d.uin, gh, d.g, P, d.off_odd, (R*)stats, nwaves, nbp);
+    hipLaunchKernelGGL((k_odd<K, STATS, PROBES>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.wave_idx,
+                       d.wave_tab, d.uin, (const typename C::store*)d.ghost, d.g, P, d.off_odd, (R*)stats, pr, nwaves,
+                       nbp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_general_odd(d, stats, s);
+}
+
+template <int K>
+static hipError_t launch_fused(const DevCtx& d, int odd, void* stats, void* probe_acc, hipStream_t s)
+{
+    if (stats && probe_acc) return hipErrorInvalidValue;
+    const StepProbes pr{d.probes.bits, d.probes.cell, d.probes.id, d.probes.n, probe_acc};
+    if (probe_acc) return pr.n > 0 ? launch_fused_k<K, false, true>(d, odd, stats, pr, s) : hipErrorInvalidValue;
+    if (stats) return launch_fused_k<K, true, false>(d, odd, stats, pr, s);
+    return launch_fused_k<K, false, false>(d, odd, stats, pr, s);
 }
 
 template <int K>
@@ -572,13 +621,13 @@ hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t 
     }
 }
 
-hipError_t launch_step(const DevCtx& d, int odd, void* stats, hipStream_t s)
+hipError_t launch_step(const DevCtx& d, int odd, void* stats, void* probe_acc, hipStream_t s)
 {
     switch (d.codec) {
-        case 0: return launch_fused<0>(d, odd, stats, s);
-        case 1: return launch_fused<1>(d, odd, stats, s);
-        case 2: return launch_fused<2>(d, odd, stats, s);
-        case 3: return launch_fused<3>(d, odd, stats, s);
+        case 0: return launch_fused<0>(d, odd, stats, probe_acc, s);
+        case 1: return launch_fused<1>(d, odd, stats, probe_acc, s);
+        case 2: return launch_fused<2>(d, odd, stats, probe_acc, s);
+        case 3: return launch_fused<3>(d, odd, stats, probe_acc, s);
         default: return hipErrorInvalidValue;
     }
 }

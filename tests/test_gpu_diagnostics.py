@@ -157,6 +157,77 @@ def test_probe_accumulator_and_stats_reduced_precision(storage):
     assert np.all(err <= bar)
 
 
+def _probe_set(w, case):
+    """Probe cells for the in-kernel sampling test: the workload's probes,
+    a duplicate, two neighbours in one 64-cell chunk and, per case, cells
+    next to the inflow face (inside the sponge) or one the step kernels do
+    not sample (the inflow face itself)."""
+    fl = fluid_mask(w)
+    p = [tuple(int(v) for v in q) for q in w.probes]
+    p.append(p[0])                                   # the same cell twice
+    x, y, z = p[1]
+    for dx in (1, -1, 2, -2):
+        if 1 <= x + dx <= w.nx - 2 and fl[z, y, x + dx] and (x + dx) // 64 == x // 64:
+            p.append((x + dx, y, z))
+            break
+    if case == "sponge":
+        zz, yy = np.nonzero(fl[:, :, 2])
+        p += [(2, int(yy[k]), int(zz[k])) for k in (0, len(zz) // 2)]
+        p.append((1, int(yy[-1]), int(zz[-1])) if fl[int(zz[-1]), int(yy[-1]), 1] else p[0])
+    if case == "inflow_face":
+        zz, yy = np.nonzero(~w.solid.astype(bool)[:, :, 0])
+        p.append((0, int(yy[len(yy) // 2]), int(zz[len(zz) // 2])))
+    return np.asarray(p, np.int64)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("case", ["interior", "stats_watchdog", "sponge", "inflow_face"])
+def test_step_probed_in_kernel_samples_equal_probe_kernel(storage, case):
+    """lbm_step_probed(n) takes most probe samples inside the step kernels;
+    its accumulator, state and statistics must equal, bit for bit, those of n
+    single steps each followed by lbm_probe_accumulate (the probe kernel).
+    Cases: interior probes only; statistics every 3 steps with the watchdog
+    every 4 (samples move between the two paths); probes in the sponge layer
+    (the sample is the velocity before nudging); a probe on the inflow face,
+    which the step kernels do not sample (the whole set then goes through
+    the probe kernel)."""
+    print(f"case: urban 96x80x40 {storage}, in-kernel probe samples, {case}", flush=True)
+    w = workloads.urban_block(storage, 30, 96, 80, 40, hmax=24, nprobes=12, seed=5, probe_seed=6, noise_seed=7,
+                              margin_x=8)
+    probes = _probe_set(w, case)
+    kw = {"watchdog_stride": 4} if case == "stats_watchdog" else {}
+    accs, states, stats = [], [], []
+    for mode in ("probed", "separate"):
+        lat = binding.from_workload(w, **kw)
+        if case == "sponge":
+            lat.set_sponge(8, 0.05)
+        lat.step(7)
+        lat.set_probes(probes)
+        acc = torch.zeros(2, len(probes), 3, dtype=lat.real_dtype, device="cuda")
+        st = torch.zeros(6, w.nz, w.ny, w.nx, dtype=lat.real_dtype, device="cuda")
+        if case == "stats_watchdog":
+            lat.set_stats(st, 3)
+        if mode == "probed":
+            lat.step_probed(13, acc)
+            lat.step_probed(1, acc)
+            lat.step_probed(10, acc)
+        else:
+            for _ in range(24):
+                lat.step(1)
+                lat.probe_accumulate(acc)
+        torch.cuda.synchronize()
+        accs.append(acc.clone())
+        states.append(lat.get_state()[0].clone())
+        stats.append(st.clone())
+        lat.close()
+    assert torch.equal(states[0], states[1])
+    assert torch.equal(stats[0], stats[1])
+    d = (accs[0] - accs[1]).abs().max().item()
+    print(f"{storage} {case}: {len(probes)} probes, max |acc difference| {d:.3e}", flush=True)
+    assert torch.equal(accs[0], accs[1])
+    assert float(accs[0][0].abs().sum()) > 0.0
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_kilometre_grid_mass_against_fp64_sum(storage):
     """82M cells: lbm_mass against an FP64 sum of the exported state over the
