@@ -252,7 +252,11 @@ int lbm_step(lbm_ctx *ctx, int64_t n);
  * probe cell (lbm_set_probes) to acc: device real [2][np][3], a
  * Neumaier-compensated sum: acc[0] the running sum, acc[1] the accumulated
  * rounding errors; the accumulated value is acc[0] + acc[1].  The caller
- * zeroes acc before the first call of a sum. */
+ * zeroes acc before the first call of a sum.  The step kernels take the
+ * samples of the states they start from when every probe is a fluid,
+ * non-inflow cell off the x faces in a row the fast kernels run; the other
+ * samples go through the probe kernel (lbm_probe_accumulate); both give the
+ * same bits. */
 int lbm_step_probed(lbm_ctx *ctx, int64_t n, void *acc);
 
 /* Macroscopic fields of the current state (eq. D.1; nu_t from eqs. D.6, D.11
