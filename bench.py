@@ -333,6 +333,61 @@ def cpu_baseline(w, seconds=12.0, crop=(160, 160)):
             "cpu_model": model, "nproc": usable, "logical_cpus": logical}
 
 
+def oracle_configs(adjoint_steps=50):
+    """The FP64 oracle (single thread) on the configurations small enough to
+    run whole: the 64x48x32 cube flow and the 128x128x64 urban subdomain for
+    100 steps each, and the adjoint copy (64x64x32): adjoint_steps forward
+    steps from the initial state, then as many adjoint steps back over the
+    stored trajectory.  Opt-in (--oracle-configs): about two minutes."""
+    import numpy as np
+
+    import oracle
+    from paper_2607_04516_amd import workloads
+    faces = {"periodic": oracle.PERIODIC, "inflow": oracle.INFLOW_EQ, "outflow": oracle.OUTFLOW_ZG,
+             "freeslip": oracle.FREESLIP, "wall": oracle.WALL}
+
+    def make(w):
+        return oracle.Oracle(w.nx, w.ny, w.nz, [faces[f] for f in w.faces], tau0=w.tau0, c_smag=w.c_smag,
+                             delta=w.delta, solid=w.solid, inflow=w.inflow, force=w.force)
+
+    def fluid(w):
+        return int(w.solid.size - np.count_nonzero(w.solid))
+
+    out = {}
+    for key, w in (("cube_64x48x32", workloads.cube_flow("f64", 100)),
+                   ("urban_subdomain_128x128x64", workloads.urban_subdomain("f64", 100))):
+        o = make(w)
+        f = o.init(u0=w.u0, amp=w.noise_amp, seed=w.noise_seed)
+        t0 = time.perf_counter()
+        for _ in range(100):
+            f = o.step(f)
+        el = time.perf_counter() - t0
+        out[key] = {"steps": 100, "seconds": round(el, 2), "mlups": round(fluid(w) * 100 / el / 1e6, 3)}
+    w = workloads.adjoint_urban("f64", adjoint_steps, small=True)
+    o = make(w)
+    f = o.init(u0=w.u0, amp=w.noise_amp, seed=w.noise_seed)
+    pr = np.asarray(w.probes, np.int32)
+    traj = [f]
+    t0 = time.perf_counter()
+    for _ in range(adjoint_steps):
+        traj.append(o.step(traj[-1]))
+    t_fwd = time.perf_counter() - t0
+    src = np.full((len(pr), 3), 1.0 / adjoint_steps)
+    lam = np.zeros((19, w.nz, w.ny, w.nx))
+    t0 = time.perf_counter()
+    for t in range(adjoint_steps, 0, -1):
+        lam, _ = o.adjoint_step(traj[t], lam, pr, src)
+    t_adj = time.perf_counter() - t0
+    n = fluid(w) * adjoint_steps / 1e6
+    out["adjoint_copy_64x64x32"] = {"steps": adjoint_steps, "forward_seconds": round(t_fwd, 2),
+                                    "adjoint_seconds": round(t_adj, 2), "forward_mlups": round(n / t_fwd, 3),
+                                    "adjoint_mlups": round(n / t_adj, 3),
+                                    "adjoint_over_forward": round(t_adj / t_fwd, 2)}
+    model, usable, logical = cpu_info()
+    return {"kind": "oracle", "threads": 1, "cpu_model": model, "nproc": usable, "logical_cpus": logical,
+            "configs": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +406,8 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint-cost workload and print its record (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=1000, help="time steps T of the adjoint workload")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="time the FP64 oracle on the small configurations (cube, subdomain, adjoint copy) and exit")
     ap.add_argument("--cpu-omp-only", action="store_true",
                     help="time only the OpenMP build of the oracle on a crop and print its record")
     ap.add_argument("--cpu-crop", type=int, nargs=2, default=(160, 160))
@@ -364,6 +421,10 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU slab decomposition is a design, not a measured path)", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_configs:
+        print(json.dumps({"oracle_configs": oracle_configs()}), flush=True)
+        return
 
     if args.cpu_omp_only:
         from paper_2607_04516_amd import workloads
