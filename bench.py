@@ -265,6 +265,17 @@ def traffic_from_profiles(storage):
     return rec["per_launch_bytes"][storage], rec.get("sources_sha256")
 
 
+def traffic_request_sizes(storage):
+    """The same per-launch bytes counted a second way (L2 -> memory read
+    requests weighted by their size, 32/64/128 B, plus write requests of 64
+    and 32 B), from the same summary; None when stale or absent."""
+    tb, sha = traffic_from_profiles(storage)
+    if tb is None:
+        return None
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_k_even_k_odd_urban_km_800x800x128.json")))
+    return rec.get("per_launch_bytes_request_sizes", {}).get(storage)
+
+
 def cpu_info():
     """(CPU model name, cores this process may use, logical CPUs of the host)."""
     model = None
@@ -534,6 +545,7 @@ def main():
                      "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (res["kernel_ms"] * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic,
+                     "traffic_bytes_per_launch_request_sizes": traffic_request_sizes(args.storage),
                      "kernel": "lbm::k_even / lbm::k_odd (alternating A-A launches, averaged)",
                      "kernel_ms": round(res["kernel_ms"], 4),
                      "bytes_per_launch": res["bytes_per_launch"],
