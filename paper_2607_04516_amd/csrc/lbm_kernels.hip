@@ -536,19 +536,6 @@ hipError_t launch_wave_masks(const DevCtx& d, int* idx, uint64_t* tab, int pass,
 
 static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <int K, int MODE, bool ST>
-static hipError_t step_k(const DevCtx& d, const void* src, void* dst, Lay ls, Lay ld, void* stats, hipStream_t s)
-{
-    using C = Codec<K>;
-    const long long nwaves = (long long)d.g.ncx * d.g.ny * d.g.nz;
-    const long long nb = (nwaves + 3) / 4;
-    const long long nbp = (nb + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_step<K, MODE, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)dst,
-                       (const typename C::store*)src, d.mask, d.uin, (const typename C::store*)d.ghost, d.g, ls, ld,
-                       phys_of<K>(d), (typename C::real*)stats, nwaves, nbp, (const unsigned*)nullptr);
-    return hipGetLastError();
-}
-
 // General odd-step kernel over the listed waves (rows on a y or z face, x
 // faces other than inflow at x- / outflow at x+).
 template <int K, bool ST>
@@ -566,17 +553,6 @@ static hipError_t general_odd_k(const DevCtx& d, void* stats, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int K>
-static hipError_t step_dispatch(const DevCtx& d, int mode, const void* src, void* dst, Lay ls, Lay ld, void* stats,
-                                hipStream_t s)
-{
-    if (mode == MODE_EVEN) return stats ? step_k<K, MODE_EVEN, true>(d, src, dst, ls, ld, stats, s)
-                                        : step_k<K, MODE_EVEN, false>(d, src, dst, ls, ld, stats, s);
-    if (mode == MODE_ODD) return stats ? step_k<K, MODE_ODD, true>(d, src, dst, ls, ld, stats, s)
-                                       : step_k<K, MODE_ODD, false>(d, src, dst, ls, ld, stats, s);
-    return step_k<K, MODE_PUSH, false>(d, src, dst, ls, ld, nullptr, s);
-}
-
 #define LBM_DISPATCH(codec, ...)                      \
     switch (codec) {                                  \
         case 0: { constexpr int K = 0; __VA_ARGS__; } \
@@ -588,11 +564,6 @@ static hipError_t step_dispatch(const DevCtx& d, int mode, const void* src, void
 
 static Lay padded(const DevCtx& d) { return Lay{d.g.S, d.g.pitch, d.g.lrb}; }
 static Lay canonical(const DevCtx& d) { return Lay{d.g.N, d.g.nx, -1}; }
-
-hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s)
-{
-    LBM_DISPATCH(d.codec, return step_dispatch<K>(d, odd ? MODE_ODD : MODE_EVEN, d.f, d.f, padded(d), padded(d), stats, s));
-}
 
 hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s)
 {

@@ -222,7 +222,6 @@ __host__ __device__ inline bool odd_wave_is_general(const Geo& g, int cx, int y,
 // probe_acc: NULL, or the accumulator the step kernels add the probe
 // velocities of the state at the step's start to (not together with stats).
 hipError_t launch_step(const DevCtx& d, int odd, void* stats, void* probe_acc, hipStream_t s);
-hipError_t launch_step_general(const DevCtx& d, int odd, void* stats, hipStream_t s);
 hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s);
 hipError_t launch_push(const DevCtx& d, const void* src, void* dst, hipStream_t s);
 hipError_t launch_outflow_ghost(const DevCtx& d, hipStream_t s);
