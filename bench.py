@@ -248,9 +248,22 @@ def copy_bandwidth():
 STEP_KERNEL_SOURCES = ("lbm_step.hip", "lbm_device.h", "lbm_launch.h", "lbm_general.h")
 
 
-def traffic_from_profiles(storage):
+def layout_string(ny):
+    """The in-place array's layout as lbm_create chooses it: R = 2^k <= 32
+    rows per block, the largest R whose padding of ny to whole blocks stays
+    within ny / 16 rows."""
+    k = 5
+    while k > 0 and (-(-ny // (1 << k)) * (1 << k) - ny) * 16 > ny:
+        k -= 1
+    r = 1 << k
+    nyp = -(-ny // r) * r
+    return f"row blocks [nyp*nz/{r}][19][{r} rows][x_pitch64], nyp = {nyp}, in-place A-A"
+
+
+def traffic_from_profiles(storage, workload):
     """HBM bytes per step-kernel launch from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+    if it was taken on this workload and the current kernel sources (else
+    None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_k_even_k_odd_urban_km_800x800x128.json")
     if not os.path.exists(path):
@@ -260,16 +273,17 @@ def traffic_from_profiles(storage):
     csrc = os.path.join(ROOT, "paper_2607_04516_amd", "csrc")
     for f in STEP_KERNEL_SOURCES:
         h.update(open(os.path.join(csrc, f), "rb").read())
-    if rec.get("sources_sha256") != h.hexdigest() or storage not in rec.get("per_launch_bytes", {}):
+    if (rec.get("sources_sha256") != h.hexdigest() or rec.get("workload") != workload
+            or storage not in rec.get("per_launch_bytes", {})):
         return None, rec.get("sources_sha256")
     return rec["per_launch_bytes"][storage], rec.get("sources_sha256")
 
 
-def traffic_request_sizes(storage):
+def traffic_request_sizes(storage, workload):
     """The same per-launch bytes counted a second way (L2 -> memory read
     requests weighted by their size, 32/64/128 B, plus write requests of 64
     and 32 B), from the same summary; None when stale or absent."""
-    tb, sha = traffic_from_profiles(storage)
+    tb, sha = traffic_from_profiles(storage, workload)
     if tb is None:
         return None
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_k_even_k_odd_urban_km_800x800x128.json")))
@@ -477,7 +491,7 @@ def main():
     if not args.no_extra:
         for s in ("f16s", "bf16s"):
             r = time_forward(w, s, args.steps, args.warmup)
-            tb, _ = traffic_from_profiles(s)
+            tb, _ = traffic_from_profiles(s, w.name)
             extra[s] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
                         "kernel_ms": round(r["kernel_ms"], 4), "achieved_gbs": round(r["achieved_gbs"], 1),
                         "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
@@ -504,7 +518,7 @@ def main():
         shard = time_shard(w, 8, min(args.steps, 40), args.warmup)
         print(f"[bench] shard: {shard}", file=sys.stderr, flush=True)
 
-    traffic, _ = traffic_from_profiles(args.storage)
+    traffic, _ = traffic_from_profiles(args.storage, w.name)
 
     adj = None
     if not args.no_adjoint:
@@ -540,12 +554,12 @@ def main():
         "config": {"workload": f"{w.name}: urban buildings PAF 0.30, median 12, power-law inflow 30 deg "
                                f"on x-/y-, outflow x+/y+, wall ground, free-slip top, tau0 0.505, C 0.1",
                    "cells": w.cells, "fluid_cells": res["fluid_cells"], "storage": args.storage,
-                   "layout": "row blocks [ny*nz/32][19][32 rows][x_pitch64], in-place A-A"},
+                   "layout": layout_string(w.ny)},
         "roofline": {"bound": "hbm", "achieved": round(res["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (res["kernel_ms"] * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic,
-                     "traffic_bytes_per_launch_request_sizes": traffic_request_sizes(args.storage),
+                     "traffic_bytes_per_launch_request_sizes": traffic_request_sizes(args.storage, w.name),
                      "kernel": "lbm::k_even / lbm::k_odd (alternating A-A launches, averaged)",
                      "kernel_ms": round(res["kernel_ms"], 4),
                      "bytes_per_launch": res["bytes_per_launch"],

@@ -134,10 +134,11 @@ struct Geo {
     int nx, ny, nz;
     int pitch;           // x pitch of the in-place population array (multiple of 64)
     int lrb;             // log2 of the rows per block of the in-place array (row blocks, below)
+    int nyp;             // rows per z plane of the in-place array: ny rounded up to whole blocks
     int wpr;             // 64-bit mask words per row
     int ncx;             // 64-cell chunks per row = pitch / 64
     int face[6];         // face kinds, order x-, x+, y-, y+, z-, z+
-    long long S;         // pitch*ny*nz: elements of one population over the grid
+    long long S;         // pitch*nyp*nz: elements of one population over the grid
     long long N;         // nx*ny*nz
     long long ghost_off[6];  // element offset of each outflow face's ghost block
     long long in_off[6];     // first per-cell inflow entry of each INFLOW_EQ face (-1: none)
@@ -207,12 +208,15 @@ __device__ inline void cell_force(const Phys<R>& P, R mx, R my, R mz, R& Fx, R& 
     }
 }
 
-// Layout of one population array.  Rows are numbered row = y + ny*z.
-//   plain (lrb < 0): slices, index = dir*S + x + pitch*row;
+// Layout of one population array.  Rows are numbered row = y + nyr*z, nyr
+// the rows per z plane in memory.
+//   plain (lrb < 0): slices, nyr = ny, index = dir*S + x + pitch*row;
 //   row blocks (lrb >= 0): R = 2^lrb consecutive rows hold their 19
 //     populations together, [row / R][dir][row % R][pitch]: index =
-//     ((row / R * 19 + dir) * R + row % R) * pitch + x.  R divides ny, so a
-//     neighbour in z sits ny / R blocks away at the same place in its block.
+//     ((row / R * 19 + dir) * R + row % R) * pitch + x.  nyr is ny rounded
+//     up to a multiple of R (the rows beyond ny are padding no kernel
+//     touches), so a neighbour in z sits nyr / R blocks away at the same
+//     place in its block.
 // The in-place array of a context uses row blocks (the 19 streams of a
 // step then fall into a few MiB instead of 19 slices 0.3 GiB apart, which
 // the DRAM serves measurably faster); canonical arrays are plain slices.
@@ -220,6 +224,7 @@ struct Lay {
     long long S;  // plain: slice stride in elements
     int pitch;    // row length in elements
     int lrb;      // log2 rows per block; -1: plain slices
+    int nyr;      // rows per z plane
 };
 
 __host__ __device__ inline long long pop_index_row(const Lay& L, int dir, long long row, int x)
@@ -229,9 +234,9 @@ __host__ __device__ inline long long pop_index_row(const Lay& L, int dir, long l
     return ((((row >> L.lrb) * NQ + dir) << L.lrb) + (row & rmask)) * L.pitch + x;
 }
 
-__host__ __device__ inline long long pop_index(const Lay& L, int ny, int dir, int x, int y, int z)
+__host__ __device__ inline long long pop_index(const Lay& L, int dir, int x, int y, int z)
 {
-    return pop_index_row(L, dir, (long long)y + (long long)ny * z, x);
+    return pop_index_row(L, dir, (long long)y + (long long)L.nyr * z, x);
 }
 
 __device__ inline bool solid_at(const uint64_t* __restrict__ mask, const Geo& g, int x, int y, int z)

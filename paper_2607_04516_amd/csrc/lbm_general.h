@@ -34,7 +34,7 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
         if constexpr (MODE == MODE_PUSH) {
             static_for<0, NQ>([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
-                dst[pop_index(ld, g.ny, I, x, y, z)] = C::enc(R(0));
+                dst[pop_index(ld, I, x, y, z)] = C::enc(R(0));
             });
         }
         return;
@@ -51,17 +51,17 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             if constexpr (MODE == MODE_EVEN) {
-                dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[opp(I)]);
+                dst[pop_index(ld, I, x, y, z)] = C::pack(h[opp(I)]);
             } else if constexpr (MODE == MODE_PUSH) {
                 // canonical output of an inflow cell is its own equilibrium
-                dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[I]);
+                dst[pop_index(ld, I, x, y, z)] = C::pack(h[I]);
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
-                    dst[pop_index(ld, g.ny, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                    dst[pop_index(ld, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
             } else {
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0)
-                    dst[pop_index(ld, g.ny, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                    dst[pop_index(ld, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
             }
         });
     } else {
@@ -74,10 +74,10 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
                     h[I] = C::raw(ghost[ghost_index<I>(g, owner, x, y, z)]);
                 } else {
                     const Res r = resolve_plain<I>(g, mask, x, y, z);
-                    h[I] = C::raw(src[pop_index(ls, g.ny, r.dir, r.x, r.y, r.z)]);
+                    h[I] = C::raw(src[pop_index(ls, r.dir, r.x, r.y, r.z)]);
                 }
             } else {
-                h[I] = C::raw(src[pop_index(ls, g.ny, I, x, y, z)]);
+                h[I] = C::raw(src[pop_index(ls, I, x, y, z)]);
             }
         });
         R drho, tau;
@@ -86,20 +86,20 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
         static_for<0, NQ>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             if constexpr (MODE == MODE_EVEN) {
-                dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[opp(I)]);
+                dst[pop_index(ld, I, x, y, z)] = C::pack(h[opp(I)]);
             } else {
                 int qx, qy, qz, owner;
                 if (outflow_entering<I>(g, x, y, z, qx, qy, qz, owner)) {
                     // opp(I) leaves through the outflow face: kept only as the
                     // bounce-back of a solid inner neighbour
-                    if (solid_at(mask, g, qx, qy, qz)) dst[pop_index(ld, g.ny, I, x, y, z)] = C::pack(h[opp(I)]);
+                    if (solid_at(mask, g, qx, qy, qz)) dst[pop_index(ld, I, x, y, z)] = C::pack(h[opp(I)]);
                 } else {
                     const Res r = resolve_plain<I>(g, mask, x, y, z);
                     if (r.kind == 0) {
                         if constexpr (MODE == MODE_PUSH) {
                             if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
                         }
-                        dst[pop_index(ld, g.ny, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                        dst[pop_index(ld, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
                     }
                 }
             }

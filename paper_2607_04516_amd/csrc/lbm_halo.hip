@@ -74,10 +74,10 @@ k_halo(typename Codec<K>::store* __restrict__ f, const uint64_t* __restrict__ ma
             constexpr int k = y_rank<CY>(J);
             const long long b = ((long long)k * g.nz + z) * g.nx + x;
             if constexpr (!UNPACK) {
-                if constexpr (PHASE == 1) buf[b] = f[pop_index(L, g.ny, opp(J), x, real, z)];
-                else buf[b] = f[pop_index(L, g.ny, J, x, ghost, z)];
+                if constexpr (PHASE == 1) buf[b] = f[pop_index(L, opp(J), x, real, z)];
+                else buf[b] = f[pop_index(L, J, x, ghost, z)];
             } else if constexpr (PHASE == 1) {
-                f[pop_index(L, g.ny, opp(J), x, ghost, z)] = buf[b];
+                f[pop_index(L, opp(J), x, ghost, z)] = buf[b];
             } else {
                 if (own_solid) return;
                 int px = x - c.x, pz = z - c.z;
@@ -85,7 +85,7 @@ k_halo(typename Codec<K>::store* __restrict__ f, const uint64_t* __restrict__ ma
                 if (!halo_axis(pz, z, g.nz, g.face[4], g.face[5])) return;
                 if (solid_at(mask, g, px, ghost, pz)) return;
                 const typename Codec<K>::store v = buf[b];
-                f[pop_index(L, g.ny, J, x, real, z)] = v;
+                f[pop_index(L, J, x, real, z)] = v;
                 // the odd step already applied the zero-gradient outflow copy
                 // of this slot (f_J of the face cell one layer out, for J
                 // entering through an OUTFLOW x or z face) from the value
@@ -96,9 +96,9 @@ k_halo(typename Codec<K>::store* __restrict__ f, const uint64_t* __restrict__ ma
                 if constexpr (c.z == -1) { if (g.face[5] == F_OUTFLOW && z == g.nz - 2) oz = g.nz - 1; }
                 if constexpr (c.z == 1) { if (g.face[4] == F_OUTFLOW && z == 1) oz = 0; }
                 if (ox >= 0 && !solid_at(mask, g, ox, real, z) && inflow_face_of(g, ox, real, z) < 0)
-                    f[pop_index(L, g.ny, J, ox, real, z)] = v;
+                    f[pop_index(L, J, ox, real, z)] = v;
                 if (oz >= 0 && !solid_at(mask, g, x, real, oz) && inflow_face_of(g, x, real, oz) < 0)
-                    f[pop_index(L, g.ny, J, x, real, oz)] = v;
+                    f[pop_index(L, J, x, real, oz)] = v;
             }
         }
     });
@@ -109,7 +109,7 @@ hipError_t halo_k(const DevCtx& d, int phase, void* buf, hipStream_t s)
 {
     using T = typename Codec<K>::store;
     const unsigned blocks = (unsigned)(((long long)d.g.nx * d.g.nz + 255) / 256);
-    const Lay L{d.g.S, d.g.pitch, d.g.lrb};
+    const Lay L{d.g.S, d.g.pitch, d.g.lrb, d.g.nyp};
     if (phase)
         hipLaunchKernelGGL((k_halo<K, SIDE, UNPACK, 1>), dim3(blocks), dim3(256), 0, s, (T*)d.f, d.mask, d.g, L, (T*)buf);
     else

@@ -78,9 +78,9 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
             constexpr V3 c = dirv(I);
             long long idx;
             if constexpr (MODE == MODE_ODD)
-                idx = pop_index(ls, g.ny, opp(I), x - c.x, y - c.y, z - c.z);
+                idx = pop_index(ls, opp(I), x - c.x, y - c.y, z - c.z);
             else
-                idx = pop_index(ls, g.ny, I, x, y, z);
+                idx = pop_index(ls, I, x, y, z);
             h[I] = C::raw(src[idx]);
         });
         R drho, ux, uy, uz, tau;
@@ -90,9 +90,9 @@ k_step(typename Codec<K>::store* dst, const typename Codec<K>::store* src, const
             constexpr V3 c = dirv(I);
             long long idx;
             if constexpr (MODE == MODE_EVEN)
-                idx = pop_index(ld, g.ny, I, x, y, z);
+                idx = pop_index(ld, I, x, y, z);
             else
-                idx = pop_index(ld, g.ny, opp(I), x - c.x, y - c.y, z - c.z);
+                idx = pop_index(ld, opp(I), x - c.x, y - c.y, z - c.z);
             dst[idx] = C::pack(h[opp(I)]);
         });
         if constexpr (STATS) {
@@ -152,10 +152,10 @@ k_outflow_ghost(const typename Codec<K>::store* f, const uint64_t* __restrict__ 
         if (!outflow_entering<I>(g, x, y, z, qx, qy, qz, owner) || owner != F) return;
         typename Codec<K>::store v;
         if (solid_at(mask, g, qx, qy, qz)) {
-            v = f[pop_index(L, g.ny, I, x, y, z)];
+            v = f[pop_index(L, I, x, y, z)];
         } else {
             const Res r = resolve_plain<I>(g, mask, qx, qy, qz);
-            v = f[pop_index(L, g.ny, r.dir, r.x, r.y, r.z)];
+            v = f[pop_index(L, r.dir, r.x, r.y, r.z)];
         }
         ghost[ghost_index<I>(g, F, x, y, z)] = v;
     });
@@ -174,7 +174,7 @@ k_outflow_copy(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, G
         int qx, qy, qz, owner;
         if (!outflow_entering<I>(g, x, y, z, qx, qy, qz, owner) || owner != F) return;
         if (solid_at(mask, g, qx, qy, qz)) return;
-        f[pop_index(L, g.ny, I, x, y, z)] = f[pop_index(L, g.ny, I, qx, qy, qz)];
+        f[pop_index(L, I, x, y, z)] = f[pop_index(L, I, qx, qy, qz)];
     });
 }
 
@@ -190,10 +190,10 @@ __device__ inline void load_cell(const typename Codec<K>::store* f, const uint64
     static_for<0, NQ>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         if (phase == 0) {
-            out[I] = f[pop_index(L, g.ny, I, x, y, z)];
+            out[I] = f[pop_index(L, I, x, y, z)];
         } else {
             const Res r = resolve_full<I>(g, mask, x, y, z);
-            out[I] = f[pop_index(L, g.ny, r.dir, r.x, r.y, r.z)];
+            out[I] = f[pop_index(L, r.dir, r.x, r.y, r.z)];
         }
     });
 }
@@ -229,7 +229,7 @@ k_init(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
         }
         equilibrium_shifted<double>(rho0, 0.0, u[0], u[1], u[2], h);
     }
-    for (int i = 0; i < NQ; i++) f[pop_index_row(L, i, row, x)] = C::enc((typename C::real)h[i]);
+    for (int i = 0; i < NQ; i++) f[pop_index(L, i, x, y, z)] = C::enc((typename C::real)h[i]);
 }
 
 // Canonical export: dst[i][n] = h_i(x, t) (unpadded), inflow cells at their
@@ -279,7 +279,7 @@ k_import(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, Geo g, 
     const bool live = x < g.nx && !solid_at(mask, g, x, y, z) && inflow_face_of(g, x, y, z) < 0;
     const long long n = x + (long long)g.nx * row;
     for (int i = 0; i < NQ; i++)
-        f[pop_index_row(L, i, row, x)] = live ? src[(long long)i * g.N + n] : C::enc(typename C::real(0));
+        f[pop_index(L, i, x, y, z)] = live ? src[(long long)i * g.N + n] : C::enc(typename C::real(0));
 }
 
 // Macroscopic fields (rho, u, nu_t = (tau_eff - tau0)/3) of the current state.
@@ -546,7 +546,7 @@ static hipError_t general_odd_k(const DevCtx& d, void* stats, hipStream_t s)
     if (nwaves == 0) return hipSuccess;
     const long long nb = (nwaves + 3) / 4;
     const long long nbp = (nb + 7) / 8 * 8;
-    const Lay L{d.g.S, d.g.pitch, d.g.lrb};
+    const Lay L{d.g.S, d.g.pitch, d.g.lrb, d.g.nyp};
     hipLaunchKernelGGL((k_step<K, MODE_ODD, ST>), dim3((unsigned)nbp), dim3(256), 0, s, (typename C::store*)d.f,
                        (const typename C::store*)d.f, d.mask, d.uin, (const typename C::store*)d.ghost, d.g, L, L,
                        phys_of<K>(d), (typename C::real*)stats, nwaves, nbp, d.odd_list);
@@ -562,8 +562,8 @@ static hipError_t general_odd_k(const DevCtx& d, void* stats, hipStream_t s)
         default: return hipErrorInvalidValue;         \
     }
 
-static Lay padded(const DevCtx& d) { return Lay{d.g.S, d.g.pitch, d.g.lrb}; }
-static Lay canonical(const DevCtx& d) { return Lay{d.g.N, d.g.nx, -1}; }
+static Lay padded(const DevCtx& d) { return Lay{d.g.S, d.g.pitch, d.g.lrb, d.g.nyp}; }
+static Lay canonical(const DevCtx& d) { return Lay{d.g.N, d.g.nx, -1, d.g.ny}; }
 
 hipError_t launch_general_odd(const DevCtx& d, void* stats, hipStream_t s)
 {

@@ -139,16 +139,28 @@ __host__ __device__ inline long long slot_span(const int face[6])
     return 2;
 }
 
-// Element offset of slot s of the cell (x + dx, row + dy + ny dz) from slot
+// Rows per block of the in-place array, R = 2^lrb <= 32: the largest R for
+// which rounding ny up to whole blocks adds at most ny / 16 padding rows;
+// nyp = ny rounded up to a multiple of R (rows per z plane in memory).
+static inline void row_blocks(int ny, int& lrb, int& nyp)
+{
+    for (lrb = 5; lrb > 0; lrb--) {
+        const long long R = 1ll << lrb;
+        if (((ny + R - 1) / R * R - ny) * 16 <= ny) break;
+    }
+    nyp = (int)((ny + (1ll << lrb) - 1) >> lrb << lrb);
+}
+
+// Element offset of slot s of the cell (x + dx, row + dy + nyp dz) from slot
 // 0 of (x, row) in the row-block layout of the in-place array (R = 2^lrb
-// rows per block, R dividing ny, |dy| <= 1).  A neighbour in z is ny / R
+// rows per block, R dividing nyp, |dy| <= 1).  A neighbour in z is nyp / R
 // blocks away; a neighbour in y lies in the same block unless the row is the
 // first (edge bit 0, dy = -1) or last (edge bit 1, dy = +1) of its block,
 // where the step into the adjacent block adds -/+ 18 B (B = R pitch).
-static inline long long block_rel(long long pitch, long long ny, int lrb, int s, int dx, int dy, int dz, int edge)
+static inline long long block_rel(long long pitch, long long nyp, int lrb, int s, int dx, int dy, int dz, int edge)
 {
     const long long R = 1ll << lrb, B = R * pitch;
-    long long o = s * B + dx + pitch * dy + (ny / R) * dz * NQ * B;
+    long long o = s * B + dx + pitch * dy + (nyp / R) * dz * NQ * B;
     if (dy == -1 && (edge & 1)) o -= (NQ - 1) * B;
     if (dy == 1 && (edge & 2)) o += (NQ - 1) * B;
     return o;
@@ -159,7 +171,7 @@ static inline long long block_rel(long long pitch, long long ny, int lrb, int s,
 // kernels add the row start to the base and x * elem as the lane offset, so
 // lo + (x elem + on) (pull source) and lo + (x elem + oo) (own slot) are
 // exact while on, oo + pitch elem < 2^32 (checked by lbm_create).
-static inline StepOff step_offsets_blocked(long long pitch, long long ny, int lrb, int elem, int cls, int edge)
+static inline StepOff step_offsets_blocked(long long pitch, long long nyp, int lrb, int elem, int cls, int edge)
 {
     StepOff o;
     const int my = cls / 3, mz = cls % 3;
@@ -169,9 +181,9 @@ static inline StepOff step_offsets_blocked(long long pitch, long long ny, int lr
         if ((my == 1 && c.y == 1) || (my == 2 && c.y == -1)) m |= 2;
         if ((mz == 1 && c.z == 1) || (mz == 2 && c.z == -1)) m |= 4;
         const int slot = opp(mirrored(i, m));
-        const long long own = block_rel(pitch, ny, lrb, i, 0, 0, 0, edge) * elem;
+        const long long own = block_rel(pitch, nyp, lrb, i, 0, 0, 0, edge) * elem;
         const long long nb =
-            block_rel(pitch, ny, lrb, slot, -c.x, (m & 2) ? 0 : -c.y, (m & 4) ? 0 : -c.z, edge) * elem;
+            block_rel(pitch, nyp, lrb, slot, -c.x, (m & 2) ? 0 : -c.y, (m & 4) ? 0 : -c.z, edge) * elem;
         const long long lo = own < nb ? own : nb;
         o.even[i] = own;
         o.odd[i] = nb;
@@ -182,14 +194,21 @@ static inline StepOff step_offsets_blocked(long long pitch, long long ny, int lr
     return o;
 }
 
-// Byte offset of the start of row `row` (slot 0, x = 0) of the in-place array.
+// Row of (y, z) in the in-place array (y + nyp z).
+__host__ __device__ inline long long mem_row(const Geo& g, int y, int z)
+{
+    return (long long)y + (long long)g.nyp * z;
+}
+
+// Byte offset of the start of memory row `row` (slot 0, x = 0) of the
+// in-place array.
 __host__ __device__ inline long long row_start(const Geo& g, long long row, int elem)
 {
     const long long rmask = (1ll << g.lrb) - 1;
     return ((row >> g.lrb) * NQ * (rmask + 1) + (row & rmask)) * (long long)g.pitch * elem;
 }
 
-// Block-edge flags of a row (bit 0: first row of its block, bit 1: last).
+// Block-edge flags of a memory row (bit 0: first row of its block, bit 1: last).
 __host__ __device__ inline int block_edge(const Geo& g, long long row)
 {
     const long long rr = row & ((1ll << g.lrb) - 1);

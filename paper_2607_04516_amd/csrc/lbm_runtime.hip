@@ -240,7 +240,7 @@ static int build_wave_masks(lbm_ctx* c)
     std::vector<StepOff> off(54);
     const int es = (int)c->store_bytes, er = c->p.storage == LBM_F64 ? 8 : 4;
     for (int k = 0; k < 9; k++) {
-        for (int e = 0; e < 4; e++) off[4 * k + e] = step_offsets_blocked(g.pitch, g.ny, g.lrb, es, k, e);
+        for (int e = 0; e < 4; e++) off[4 * k + e] = step_offsets_blocked(g.pitch, g.nyp, g.lrb, es, k, e);
         off[36 + k] = step_offsets(g.N, g.nx, g.ny, es, k);
         off[45 + k] = step_offsets(g.N, g.nx, g.ny, er, k);
     }
@@ -287,10 +287,12 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
         // the step kernels address the two candidate slots of a direction in
         // the in-place array with 32-bit byte offsets from the nearer one: a
         // neighbour in z lies one plane of all 19 populations away
-        // (19 pitch ny elements), plus the block-edge and slot terms
+        // (19 pitch nyp elements), plus the block-edge and slot terms
         const long long pitch = ((long long)grid->nx + 63) / 64 * 64;
+        int lrb, nyp;
+        row_blocks(grid->ny, lrb, nyp);
         const long long span =
-            (NQ * pitch * grid->ny + 40 * 32 * pitch + 2 * pitch) * (long long)codec_bytes(params->storage);
+            (NQ * pitch * nyp + 40 * 32 * pitch + 2 * pitch) * (long long)codec_bytes(params->storage);
         if (span >= (1ll << 32) || (long long)grid->ny * grid->nz * (((long long)grid->nx + 63) / 64) >= (1ll << 32))
             return fail(nullptr, LBM_EINVAL,
                         "grid too large for one context (19 populations of one xy plane must stay below 4 GiB)");
@@ -336,17 +338,15 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     g.ncx = (g.nx + 63) / 64;
     g.pitch = g.ncx * 64;
     g.wpr = g.ncx;
-    // rows per block of the in-place array: the largest power of two up to
-    // 32 that divides ny (whole blocks per xy plane)
-    g.lrb = 0;
-    while (g.lrb < 5 && g.ny % (2 << g.lrb) == 0) g.lrb++;
+    // rows per block of the in-place array (each xy plane padded to whole blocks)
+    row_blocks(g.ny, g.lrb, g.nyp);
     // a ghost row is updated like a free-slip face row (its values are
     // replaced or discarded by the halo exchange)
     for (int k = 0; k < 6; k++) {
         c->halo[k] = params->face[k] == LBM_HALO;
         g.face[k] = c->halo[k] ? F_FREESLIP : params->face[k];
     }
-    g.S = (long long)g.pitch * g.ny * g.nz;
+    g.S = (long long)g.pitch * g.nyp * g.nz;
     g.N = N;
     long long goff = 0;
     for (int F = 0; F < 6; F++) {

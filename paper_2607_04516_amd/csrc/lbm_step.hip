@@ -180,7 +180,7 @@ k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const dou
     const uint64_t wrow = mask_word(mask, row * g.wpr + cx);
     if (x >= g.nx || ((wrow >> lane) & 1ull)) return;
 
-    char* base = (char*)f + row_start(g, row, (int)sizeof(T));
+    char* base = (char*)f + row_start(g, mem_row(g, y, z), (int)sizeof(T));
     const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
     R h[NQ];
     const int inf = inflow_face_of(g, x, y, z);
@@ -238,7 +238,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
     const int y = (int)(row % g.ny), z = (int)(row / g.ny);
     if (odd_general_wave(g, cx, y, z)) return;
     const int x = cx * 64 + lane;
-    const auto& O = class_offsets(otab, 4 * row_class(g, y, z) + block_edge(g, row));
+    const auto& O = class_offsets(otab, 4 * row_class(g, y, z) + block_edge(g, mem_row(g, y, z)));
     const bool x_lo = (cx == 0);                   // lane 0 is an x- inflow or wall cell
     const bool x_hi = (cx * 64 + 63 >= g.nx - 1);  // lane l_out is an x+ outflow or wall cell
     const int l_out = (g.nx - 1) - cx * 64;
@@ -279,7 +279,7 @@ k_odd(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const int*
         return m;
     };
 
-    char* base = (char*)f + row_start(g, row, (int)sizeof(T));
+    char* base = (char*)f + row_start(g, mem_row(g, y, z), (int)sizeof(T));
     const uint32_t off = (uint32_t)x * (uint32_t)sizeof(T);
     R h[NQ];
     if (!solid_any && !x_lo && !x_hi) {
@@ -411,7 +411,7 @@ k_push(const typename Codec<K>::store* __restrict__ src, typename Codec<K>::stor
         if (t >= ncells) return;
         const long long n = cells[t];
         const long long r = n / g.nx;
-        const Lay L{g.N, g.nx, -1};
+        const Lay L{g.N, g.nx, -1, g.ny};
         general_cell<K, MODE_PUSH, false>(dst, src, mask, uin, nullptr, g, L, L, P, nullptr, (int)(n % g.nx),
                                           (int)(r % g.ny), (int)(r / g.ny));
         return;
@@ -574,7 +574,7 @@ static hipError_t launch_fused_k(const DevCtx& d, int odd, void* stats, const St
     const Phys<R> P = phys_of<K>(d);
     auto* f = (typename C::store*)d.f;
     if (!odd) {
-        const StepOff O = step_offsets_blocked(d.g.pitch, d.g.ny, d.g.lrb, (int)sizeof(typename C::store), 0, 0);
+        const StepOff O = step_offsets_blocked(d.g.pitch, d.g.nyp, d.g.lrb, (int)sizeof(typename C::store), 0, 0);
         hipLaunchKernelGGL((k_even<K, STATS, PROBES>), dim3((unsigned)nbp), dim3(256), 0, s, f, d.mask, d.uin, d.g, P,
                            O, (R*)stats, pr, nwaves, nbp);
         return hipGetLastError();

@@ -56,13 +56,14 @@ static void fail(const char* what, const Geo& g, int e, int cls, int x, int y, i
     errors++;
 }
 
-// Independent element index of (slot s, x, y, z): blocked (R rows per block) or plain slices.
+// Independent element index of (slot s, x, y, z): blocked (R rows per block,
+// rows numbered y + nyr z with nyr >= ny a multiple of R) or plain slices (nyr = ny).
 struct Layout {
     bool blocked;
-    long long S, pitch, ny, R;
+    long long S, pitch, nyr, R;
     long long index(int s, int x, int y, int z) const
     {
-        const long long row = y + ny * z;
+        const long long row = y + nyr * z;
         if (!blocked) return s * S + row * pitch + x;
         return ((row / R) * 19 + s) * R * pitch + (row % R) * pitch + x;
     }
@@ -85,8 +86,10 @@ static void check(const Geo& g, const Layout& L, int e, bool adjoint)
         long long rowbase;   // what the kernel adds to the array base before the lane offset
         uint32_t off0;       // lane offset of x = 0
         if (L.blocked) {
-            O = step_offsets_blocked(g.pitch, g.ny, g.lrb, e, cls, block_edge(g, row));
-            rowbase = row_start(g, row, e);
+            const long long mrow = mem_row(g, y, z);
+            if (mrow != y + L.nyr * z) fail("mem_row", g, e, cls, 0, y, z, 0, mrow, y + L.nyr * z);
+            O = step_offsets_blocked(g.pitch, g.nyp, g.lrb, e, cls, block_edge(g, mrow));
+            rowbase = row_start(g, mrow, e);
             off0 = 0;
         } else {
             O = step_offsets(L.S, L.pitch, g.ny, e, cls);
@@ -140,20 +143,28 @@ int main()
         {1024, 1024, 127, {1, 2, 3, 3, 4, 3}},   // free-slip faces, canonical FP32 slices just below 512 MiB
         {1024, 1024, 500, {1, 2, 1, 2, 4, 4}},   // no free-slip face: canonical FP32 slices just below 2 GiB
         {4096, 4096, 40, {1, 2, 3, 3, 4, 3}},    // in-place array 48 GiB in FP64
+        {805, 897, 160, {1, 2, 1, 2, 4, 3}},     // odd ny: 32-row blocks over 928 padded rows
+        {96, 102, 40, {1, 2, 3, 3, 4, 3}},       // a slab with ghost rows: 8-row blocks over 104
     };
     for (const Case& c : cases) {
         for (int e : {8, 4, 2}) {
             Geo g{};
             g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
             g.ncx = (g.nx + 63) / 64; g.pitch = g.ncx * 64; g.wpr = g.ncx;
-            g.lrb = 0;
-            while (g.lrb < 5 && g.ny % (2 << g.lrb) == 0) g.lrb++;
+            row_blocks(g.ny, g.lrb, g.nyp);
+            const long long R = 1ll << g.lrb;
+            // padding: whole blocks, at most ny / 16 extra rows, and no smaller
+            // padding with a larger block
+            if (g.nyp % R != 0 || g.nyp < g.ny || (g.nyp - g.ny) * 16 > g.ny || g.nyp - g.ny >= R) {
+                std::printf("FAIL row blocks ny %d: lrb %d nyp %d\n", g.ny, g.lrb, g.nyp);
+                errors++;
+            }
             for (int k = 0; k < 6; k++) g.face[k] = c.face[k];
-            g.S = (long long)g.pitch * g.ny * g.nz;
+            g.S = (long long)g.pitch * g.nyp * g.nz;
             g.N = (long long)g.nx * g.ny * g.nz;
             // the in-place array (row blocks): lbm_create's limit, restated
-            if ((19ll * g.pitch * g.ny + 40ll * 32 * g.pitch + 2ll * g.pitch) * e < (1ll << 32))
-                check(g, Layout{true, g.S, g.pitch, g.ny, 1ll << g.lrb}, e, false);
+            if ((19ll * g.pitch * g.nyp + 40ll * 32 * g.pitch + 2ll * g.pitch) * e < (1ll << 32))
+                check(g, Layout{true, g.S, g.pitch, g.nyp, R}, e, false);
             // canonical arrays of the push and adjoint: eight slices with a
             // free-slip y or z face, else two, below 2^32 bytes
             bool freeslip = false;
