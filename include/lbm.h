@@ -89,13 +89,14 @@ typedef struct {
 
 /* Create a context.  solid: host uint8 [nz][ny][nx], nonzero = solid cell
  * (buildings and terrain voxels, Sec. 2.1); copied and bit-packed on the
- * device.  Allocates the population array (19 * nx_pitch * ny * nz * sizeof(store))
+ * device.  Allocates the population array (19 * nx_pitch * ny_pad * nz * sizeof(store))
  * and initialises the state at t = 0 to feq(rho0, u_init + noise) in fluid
  * cells and h = 0 in solid cells.  The array is laid out in row blocks
- * (R consecutive rows (y, z) keep their 19 populations together, R the
- * largest power of two <= 32 dividing ny), so the step kernels' 32-bit slot
- * offsets span one xy plane of all 19 populations: size limit
- * (19 * nx_pitch * ny + 1282 * nx_pitch) * sizeof(store) < 4 GiB,
+ * (R consecutive rows (y, z) keep their 19 populations together, R = 2^k <=
+ * 32 the largest block whose padding of each xy plane to ny_pad rows, a
+ * multiple of R, stays within ny / 16 rows), so the step kernels' 32-bit
+ * slot offsets span one xy plane of all 19 populations: size limit
+ * (19 * nx_pitch * ny_pad + 1282 * nx_pitch) * sizeof(store) < 4 GiB,
  * nx_pitch = nx rounded up to 64; larger grids return EINVAL.
  * lbm_push_step and lbm_adjoint_step have a tighter limit (below).  Errors:
  * EINVAL, ENOMEM, EHIP; *out is NULL on error and lbm_last_error(NULL) gives
