@@ -82,7 +82,9 @@ def _solid_small(nx, ny, nz, seed):
 
 
 @pytest.mark.parametrize("fi", range(len(FACE_SETS)))
-@pytest.mark.parametrize("dims", [(5, 4, 6), (9, 7, 4), (12, 6, 5)])
+# (70, 34, 6) and (67, 33, 5): two chunks per row, xy planes padded to
+# whole row blocks (4 rows per block over 36 rows, 2 over 34)
+@pytest.mark.parametrize("dims", [(5, 4, 6), (9, 7, 4), (12, 6, 5), (70, 34, 6), (67, 33, 5)])
 def test_boundary_matrix_stepwise_f64(fi, dims):
     faces = FACE_SETS[fi]
     nx, ny, nz = dims
