@@ -181,7 +181,7 @@ def _probe_set(w, case):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
-@pytest.mark.parametrize("case", ["interior", "stats_watchdog", "sponge", "inflow_face"])
+@pytest.mark.parametrize("case", ["interior", "stats_watchdog", "sponge", "inflow_face", "padded_plane"])
 def test_step_probed_in_kernel_samples_equal_probe_kernel(storage, case):
     """lbm_step_probed(n) takes most probe samples inside the step kernels;
     its accumulator, state and statistics must equal, bit for bit, those of n
@@ -190,9 +190,11 @@ def test_step_probed_in_kernel_samples_equal_probe_kernel(storage, case):
     every 4 (samples move between the two paths); probes in the sponge layer
     (the sample is the velocity before nudging); a probe on the inflow face,
     which the step kernels do not sample (the whole set then goes through
-    the probe kernel)."""
-    print(f"case: urban 96x80x40 {storage}, in-kernel probe samples, {case}", flush=True)
-    w = workloads.urban_block(storage, 30, 96, 80, 40, hmax=24, nprobes=12, seed=5, probe_seed=6, noise_seed=7,
+    the probe kernel); and interior probes on a grid whose xy planes are
+    padded to whole row blocks (ny = 75: 4-row blocks over 76 rows)."""
+    ny = 75 if case == "padded_plane" else 80
+    print(f"case: urban 96x{ny}x40 {storage}, in-kernel probe samples, {case}", flush=True)
+    w = workloads.urban_block(storage, 30, 96, ny, 40, hmax=24, nprobes=12, seed=5, probe_seed=6, noise_seed=7,
                               margin_x=8)
     probes = _probe_set(w, case)
     kw = {"watchdog_stride": 4} if case == "stats_watchdog" else {}
