@@ -61,6 +61,7 @@ def time_forward(w, storage, steps, warmup, setup=None):
     kern_ms, launches = lat.profile_read()
     lat.profile(False)
     fluid, _ = lat.cell_counts()
+    rows, nyp, pitch = lat.layout()
     mlups = fluid * steps / (ms * 1e-3) / 1e6
     per_launch_ms = kern_ms / max(launches, 1)
     bytes_launch = algorithmic_bytes(lat, storage)
@@ -70,7 +71,8 @@ def time_forward(w, storage, steps, warmup, setup=None):
     lat.close()
     return {"mlups": mlups, "ms_per_step": ms / steps, "kernel_ms": per_launch_ms, "launches": launches,
             "bytes_per_launch": bytes_launch, "achieved_gbs": gbs, "fluid_cells": fluid,
-            "mass": m, "energy": e}
+            "mass": m, "energy": e,
+            "layout": f"row blocks [{nyp}*nz/{rows}][19][{rows} rows][{pitch}], in-place A-A"}
 
 
 def time_adjoint(steps=1000, every=50):
@@ -246,18 +248,6 @@ def copy_bandwidth():
 # the files that define the step kernels k_even / k_odd (the counter record
 # stays valid while these are unchanged)
 STEP_KERNEL_SOURCES = ("lbm_step.hip", "lbm_device.h", "lbm_launch.h", "lbm_general.h")
-
-
-def layout_string(ny):
-    """The in-place array's layout as lbm_create chooses it: R = 2^k <= 32
-    rows per block, the largest R whose padding of ny to whole blocks stays
-    within ny / 16 rows."""
-    k = 5
-    while k > 0 and (-(-ny // (1 << k)) * (1 << k) - ny) * 16 > ny:
-        k -= 1
-    r = 1 << k
-    nyp = -(-ny // r) * r
-    return f"row blocks [nyp*nz/{r}][19][{r} rows][x_pitch64], nyp = {nyp}, in-place A-A"
 
 
 def traffic_from_profiles(storage, workload):
@@ -554,7 +544,7 @@ def main():
         "config": {"workload": f"{w.name}: urban buildings PAF 0.30, median 12, power-law inflow 30 deg "
                                f"on x-/y-, outflow x+/y+, wall ground, free-slip top, tau0 0.505, C 0.1",
                    "cells": w.cells, "fluid_cells": res["fluid_cells"], "storage": args.storage,
-                   "layout": layout_string(w.ny)},
+                   "layout": res["layout"]},
         "roofline": {"bound": "hbm", "achieved": round(res["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(res["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (res["kernel_ms"] * 1e-3) / 1e9, 1),

@@ -409,6 +409,11 @@ int64_t lbm_time(const lbm_ctx *ctx);
  * cells counted by lbm_mass (non-solid, non-inflow). */
 int lbm_cell_counts(const lbm_ctx *ctx, int64_t *fluid, int64_t *interior);
 
+/* Layout of the context's in-place population array (see lbm_create):
+ * rows per block R, rows per xy plane ny_pad (ny rounded up to a multiple of
+ * R) and the x pitch nx_pitch; any may be NULL. */
+int lbm_layout(const lbm_ctx *ctx, int32_t *rows_per_block, int32_t *ny_pad, int32_t *nx_pitch);
+
 /* Replace the HIP stream work is enqueued on (NULL = null stream). */
 int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
 

@@ -63,7 +63,7 @@ EXPORTS = ["lbm_create", "lbm_destroy", "lbm_set_inflow", "lbm_set_inflow_face",
            "lbm_reset", "lbm_step", "lbm_step_probed",
            "lbm_macros", "lbm_probe", "lbm_probe_noalloc", "lbm_mass", "lbm_get_state", "lbm_set_state", "lbm_set_probes",
            "lbm_probe_accumulate", "lbm_set_stats", "lbm_push_step", "lbm_adjoint_step", "lbm_time",
-           "lbm_cell_counts", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read",
+           "lbm_cell_counts", "lbm_layout", "lbm_set_stream", "lbm_last_error", "lbm_profile", "lbm_profile_read",
            "lbm_halo_pack", "lbm_halo_unpack", "lbm_voxelize"]
 
 _lib = None
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "lbm_adjoint_step": ([P, P, P, P, P, P], ctypes.c_int),
         "lbm_time": ([P], I64),
         "lbm_cell_counts": ([P, P, P], ctypes.c_int),
+        "lbm_layout": ([P, P, P, P], ctypes.c_int),
         "lbm_set_stream": ([P, P], ctypes.c_int),
         "lbm_last_error": ([P], ctypes.c_char_p),
         "lbm_profile": ([P, I32], ctypes.c_int),
@@ -305,6 +306,12 @@ class LBM:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.lbm_cell_counts(self.ctx, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def layout(self):
+        """(rows per block, rows per xy plane, x pitch) of the in-place array."""
+        r, n, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.lbm_layout(self.ctx, ctypes.byref(r), ctypes.byref(n), ctypes.byref(p)))
+        return r.value, n.value, p.value
 
     def macros(self):
         rho = torch.empty(self.nz, self.ny, self.nx, dtype=self.real_dtype, device=self.device)

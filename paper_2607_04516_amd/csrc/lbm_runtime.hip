@@ -540,6 +540,15 @@ int lbm_cell_counts(const lbm_ctx* c, int64_t* fluid, int64_t* interior)
     return LBM_OK;
 }
 
+int lbm_layout(const lbm_ctx* c, int32_t* rows_per_block, int32_t* ny_pad, int32_t* nx_pitch)
+{
+    if (!c) return LBM_EINVAL;
+    if (rows_per_block) *rows_per_block = 1 << c->d.g.lrb;
+    if (ny_pad) *ny_pad = c->d.g.nyp;
+    if (nx_pitch) *nx_pitch = c->d.g.pitch;
+    return LBM_OK;
+}
+
 int lbm_set_stream(lbm_ctx* c, void* s)
 {
     if (!c) return LBM_EINVAL;

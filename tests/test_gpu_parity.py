@@ -293,3 +293,16 @@ def test_error_paths():
     assert e.value.code == -1
     with pytest.raises(binding.LBMError):
         lat.set_inflow(1, np.zeros((4, 3)))   # x+ is an outflow face
+
+
+@pytest.mark.parametrize("dims,want", [((64, 48, 8), (16, 48, 64)), ((70, 34, 6), (4, 36, 128)),
+                                       ((67, 33, 5), (2, 34, 128)), ((9, 7, 4), (1, 7, 64)),
+                                       ((130, 897, 3), (32, 928, 192)), ((96, 102, 4), (8, 104, 128))])
+def test_layout_rows_per_block(dims, want):
+    """lbm_layout: R = 2^k <= 32 rows per block, the largest whose padding of
+    each xy plane to whole blocks stays within ny / 16 rows; x pitch = nx
+    rounded up to 64."""
+    nx, ny, nz = dims
+    lat = binding.LBM(nx, ny, nz, faces=("periodic",) * 6, tau0=0.6, storage="f32")
+    assert lat.layout() == want
+    lat.close()
