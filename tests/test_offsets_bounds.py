@@ -19,8 +19,9 @@ opp(I') of the pull source x - c' (c' = c_I with the components mirrored at
 the row's free-slip faces zeroed) whenever that source lies in the grid.
 Every address must also fall inside the population array.  The adjoint's
 outflow copies (one element further along x) and the push's inflow-cell
-store toward x = 1 are covered by the same enumeration.  Also: lbm_create
-refuses grids beyond its limit.
+store toward x = 1 are covered by the same enumeration, and the choice of
+rows per block (row_blocks) is checked against its statement for every ny
+up to 5000.  Also: lbm_create refuses grids beyond its limit.
 """
 import ctypes
 import os
@@ -128,8 +129,31 @@ static void check(const Geo& g, const Layout& L, int e, bool adjoint)
     }
 }
 
+// row_blocks against its statement for every ny up to 5000: R = 2^k <= 32,
+// nyp the next multiple of R, padding at most ny / 16, and no larger R
+// that would satisfy the same bound.
+static void check_row_blocks()
+{
+    for (int ny = 1; ny <= 5000; ny++) {
+        int lrb = -1, nyp = -1;
+        row_blocks(ny, lrb, nyp);
+        const long long R = 1ll << lrb;
+        bool ok = lrb >= 0 && lrb <= 5 && nyp % R == 0 && nyp >= ny && nyp - ny < R && (nyp - ny) * 16 <= ny;
+        if (ok && lrb < 5) {
+            const long long R2 = 2 * R, p2 = (ny + R2 - 1) / R2 * R2;
+            ok = (p2 - ny) * 16 > ny;
+        }
+        if (!ok) {
+            if (errors < 20) std::printf("FAIL row_blocks ny %d: lrb %d nyp %d\n", ny, lrb, nyp);
+            errors++;
+        }
+        checked++;
+    }
+}
+
 int main()
 {
+    check_row_blocks();
     struct Case { int nx, ny, nz; int face[6]; };
     // face kinds: 0 periodic, 1 inflow, 2 outflow, 3 free-slip, 4 wall
     std::vector<Case> cases = {
