@@ -308,3 +308,30 @@ def test_watchdog_quiet_on_a_stable_run():
     lat = binding.from_workload(w, watchdog_stride=7)
     lat.step(50)
     assert lat.time == 50
+
+
+def test_watchdog_recovery_from_checkpoint():
+    """Recovery after EUNSTABLE: the checkpoint taken before the failure is
+    imported into a context with a stable relaxation time and the run goes
+    on; the restored context matches one started from the same checkpoint."""
+    w = _cube_small(tau0=0.5001, u=0.25, c_smag=0.0)
+    lat = binding.from_workload(w, watchdog_stride=10)
+    lat.step(2)
+    ck, t = lat.get_state()
+    ck = ck.clone()
+    with pytest.raises(binding.LBMError) as e:
+        lat.step(2000)
+    assert e.value.code == -4
+    lat.close()
+    ws = _cube_small(tau0=0.52, u=0.25, c_smag=0.1)
+    runs = []
+    for _ in range(2):
+        r = binding.from_workload(ws, watchdog_stride=10)
+        r.set_state(ck, t)
+        r.step(100)
+        assert r.time == t + 100
+        m, en = r.mass()
+        assert np.isfinite(m) and np.isfinite(en)
+        runs.append(r.get_state()[0].clone())
+        r.close()
+    assert torch.equal(runs[0], runs[1])
