@@ -157,6 +157,32 @@ static std::vector<unsigned> block_schedule(const Geo& g, const std::vector<unsi
     return out;
 }
 
+// Hardware block i of a launch runs on XCD i % 8, each XCD with its own L2.
+// group_on_xcds reorders a block schedule so that G consecutive entries run
+// on one XCD: it pads the schedule with no-op entries (a wave block beyond
+// the grid, which the kernels skip) to a multiple of 8 G and gives hardware
+// block i the entry at (slot / G) 8 G + (i % 8) G + slot % G, slot = i / 8.
+// Neighbouring wave blocks of the push and adjoint launches share the lines
+// at their chunk and row edges; with G = 4 on the 256x256x96 grid the push
+// step took 201 instead of 215 us and the adjoint step 260 instead of 264 us
+// (G = 2: 206 / 264, G = 8: 200 / 261, G = 16: 198 / 264).
+constexpr int SCHED_XCD_GROUP = 4;
+
+static void group_on_xcds(std::vector<unsigned>& s, long long nwaves, int G)
+{
+    const unsigned beyond = (unsigned)((nwaves + 3) / 4);
+    if (G <= 1 || beyond >= (1u << 30)) return;
+    const unsigned noop = (2u << 30) | beyond;
+    const size_t m = (size_t)8 * G;
+    std::vector<unsigned> p = s;
+    while (p.size() % m) p.push_back(noop);
+    s.resize(p.size());
+    for (size_t i = 0; i < p.size(); i++) {
+        const size_t slot = i >> 3, x = i & 7;
+        s[i] = p[(slot / G) * m + x * G + slot % G];
+    }
+}
+
 static bool has_halo(const lbm_ctx* c)
 {
     return c->halo[2] || c->halo[3];
@@ -463,7 +489,9 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid, const lbm_params* par
     c->d.adj_list = c->adj_list;
     c->d.adj_list_n = (long long)alist.size();
     {
-        const std::vector<unsigned> sp = block_schedule(g, plist, false), sa = block_schedule(g, alist, true);
+        std::vector<unsigned> sp = block_schedule(g, plist, false), sa = block_schedule(g, alist, true);
+        group_on_xcds(sp, (long long)g.ncx * g.ny * g.nz, SCHED_XCD_GROUP);
+        group_on_xcds(sa, (long long)g.ncx * g.ny * g.nz, SCHED_XCD_GROUP);
         if ((rc = device_alloc(c, (void**)&c->push_sched, sp.size() * sizeof(unsigned), "block order")) != LBM_OK ||
             (rc = device_alloc(c, (void**)&c->adj_sched, sa.size() * sizeof(unsigned), "block order")) != LBM_OK) {
             g_create_error = c->err;
