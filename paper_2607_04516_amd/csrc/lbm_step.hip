@@ -164,10 +164,12 @@ __device__ inline void step_probe_add(const StepProbes& pr, long long cell, long
 }
 
 // ---------------------------------------------------------------- even step
-// FP32 without statistics: eight waves per SIMD (the SGPR count otherwise
-// limits the kernel to seven), 5% faster; the 16-bit forms are slower so.
+// Occupancy is left to the compiler (seven waves per SIMD at FP32, its
+// scalar registers): asking for eight, which made it spill scalar registers
+// into vector lanes, was 2.3% slower on the kilometre grid and 2.9% on the
+// 256x256x96 grid with the current streaming hints.
 template <int K, bool STATS, bool PROBES>
-__global__ void __launch_bounds__(256, (K == 1 && !STATS && !PROBES) ? 8 : 1)
+__global__ void __launch_bounds__(256)
 k_even(typename Codec<K>::store* f, const uint64_t* __restrict__ mask, const double* __restrict__ uin, Geo g,
        Phys<typename Codec<K>::real> P, StepOff O, typename Codec<K>::real* stats, StepProbes pr, long long nwaves)
 {
