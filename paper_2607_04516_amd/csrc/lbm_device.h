@@ -359,9 +359,12 @@ __device__ inline bool outflow_entering(const Geo& g, int x, int y, int z, int& 
     return moved;
 }
 
-// Index of the ghost entry for (face, direction I, cell p).
-template <int I>
-__device__ inline long long ghost_index(const Geo& g, int face, int x, int y, int z)
+// Index of the ghost entry for (face, direction I, cell p).  With AT the
+// face's first entry is goff instead of g.ghost_off[face] (a caller whose
+// face index is not a kernel argument passes it in, so that the by-value
+// descriptor is not indexed at run time).
+template <int I, bool AT = false>
+__device__ inline long long ghost_index(const Geo& g, int face, int x, int y, int z, long long goff = 0)
 {
     const int a = face >> 1;
     const int s = (face & 1) ? -1 : 1;
@@ -371,7 +374,8 @@ __device__ inline long long ghost_index(const Geo& g, int face, int x, int y, in
     else if (a == 1) { k = entering_rank(I, 1, s); cell = x + (long long)g.nx * z; }
     else { k = entering_rank(I, 2, s); cell = x + (long long)g.nx * y; }
     long long fc = (a == 0) ? (long long)g.ny * g.nz : (a == 1 ? (long long)g.nx * g.nz : (long long)g.nx * g.ny);
-    return g.ghost_off[face] + (long long)k * fc + cell;
+    if constexpr (AT) return goff + (long long)k * fc + cell;
+    else return g.ghost_off[face] + (long long)k * fc + cell;
 }
 
 // Full resolution of the pull of direction I at a fluid (non-solid,

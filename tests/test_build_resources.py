@@ -20,7 +20,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(build_lib.HIPCC), reason="hip
 # (source, kernel-name pattern); codecs 1..3 (FP32, binary16, bfloat16)
 HOT = [("lbm_step.hip", r"k_(even|odd|push)ILi[123]E"),
        ("lbm_adjoint.hip", r"k_adjointILi[123]E"),
-       ("lbm_kernels.hip", r"k_stepILi[123]E")]
+       ("lbm_kernels.hip", r"k_(step|outflow_ghost|outflow_copy)ILi[123]E")]
 
 
 def _resources(src):
