@@ -27,6 +27,36 @@ struct AdjProbes {
 // The same table for the forward step kernels, which add u of the state a
 // step starts from to the probes' compensated sums acc [2][np][3] (real
 // type of the codec).
+// Division of a 32-bit n by a run-time invariant divisor d (1 <= d < 2^32)
+// as a multiply-high and two shifts whose constants the host fixes once
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994, Fig. 4.1): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1 (which fits 32 bits), t = hi32(m n) and
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0).
+struct FastDiv {
+    uint32_t m, s1, s2;
+};
+
+inline FastDiv fast_div(uint32_t d)
+{
+    int l = 0;
+    while ((1ull << l) < d) l++;
+    const uint64_t m = ((((1ull << l) - d) << 32) / d) + 1;
+    return FastDiv{(uint32_t)m, (uint32_t)(l < 1 ? l : 1), (uint32_t)(l > 1 ? l - 1 : 0)};
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f)
+{
+    const uint32_t t = (uint32_t)(((uint64_t)f.m * n) >> 32);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// The divisors of the step kernels' wave index: chunks per row, rows per
+// z plane.
+struct WaveDiv {
+    FastDiv ncx, ny;
+};
+
 struct StepProbes {
     const uint32_t* bits;
     const unsigned* cell;

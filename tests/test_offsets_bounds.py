@@ -21,7 +21,9 @@ Every address must also fall inside the population array.  The adjoint's
 outflow copies (one element further along x) and the push's inflow-cell
 store toward x = 1 are covered by the same enumeration, and the choice of
 rows per block (row_blocks) is checked against its statement for every ny
-up to 5000.  Also: lbm_create refuses grids beyond its limit.
+up to 5000, and the multiply-high division that splits the step kernels'
+wave index against the hardware division.  Also: lbm_create refuses grids
+beyond its limit.
 """
 import ctypes
 import os
@@ -151,9 +153,42 @@ static void check_row_blocks()
     }
 }
 
+// The step kernels split their wave index with multiply-high divisions
+// (fast_div / fdiv); against the hardware division for every divisor up to
+// 5000 and pseudo-random larger ones, at the range edges and at
+// pseudo-random dividends over the whole 32-bit range.
+static void check_fast_div()
+{
+    uint64_t s = 0x9e3779b97f4a7c15ull;
+    auto next = [&]() { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return (uint32_t)(s >> 32); };
+    std::vector<uint32_t> ds;
+    for (uint32_t d = 1; d <= 5000; d++) ds.push_back(d);
+    for (int k = 0; k < 2000; k++) {
+        const uint32_t d = next() >> (k % 32);
+        ds.push_back(d ? d : 1u);
+    }
+    ds.push_back(0xffffffffu);
+    ds.push_back(0x80000000u);
+    ds.push_back(0x80000001u);
+    for (uint32_t d : ds) {
+        const FastDiv f = fast_div(d);
+        auto test = [&](uint32_t n) {
+            if (fdiv(n, f) != n / d) {
+                if (errors < 20) std::printf("FAIL fdiv %u / %u: %u\n", n, d, fdiv(n, f));
+                errors++;
+            }
+            checked++;
+        };
+        for (uint32_t n : {0u, 1u, d - 1, d, d + 1, 2 * d - 1, 2 * d, 0x7fffffffu, 0x80000000u, 0xfffffffeu, 0xffffffffu})
+            test(n);
+        for (int k = 0; k < 100; k++) test(next());
+    }
+}
+
 int main()
 {
     check_row_blocks();
+    check_fast_div();
     struct Case { int nx, ny, nz; int face[6]; };
     // face kinds: 0 periodic, 1 inflow, 2 outflow, 3 free-slip, 4 wall
     std::vector<Case> cases = {
