@@ -20,6 +20,36 @@ __device__ __forceinline__ void static_for(Fn&& fn)
 
 constexpr int MODE_EVEN = 0, MODE_ODD = 1, MODE_PUSH = 2;
 
+// The zero-gradient outflow copies of slot (d, J) in the push's output
+// (J with velocity (vx, vy, vz)): f_J(c) = f_J(q) for an outflow cell c,
+// fluid and not an inflow cell, where q is c moved one cell inward along
+// every outflow face c lies on and J enters through.  The c whose q is d
+// are d moved outward along a non-empty subset of the axes where d lies
+// next to an outflow face J enters through (up to three: J has at most two
+// non-zero components), provided d itself lies on no outflow face J enters
+// through (else q(c) would move along that axis too).  The push stores
+// these copies together with the slot, so no copy pass follows it.
+template <typename T>
+__device__ __forceinline__ void store_copies(T* dst, const uint64_t* __restrict__ mask, const Geo& g, const Lay& L,
+                                             int dx, int dy, int dz, int J, int vx, int vy, int vz, T v)
+{
+    int sx = 0, sy = 0, sz = 0;
+    if (vx == -1 && g.face[1] == F_OUTFLOW) { if (dx == g.nx - 1) return; if (dx == g.nx - 2) sx = 1; }
+    if (vx == 1 && g.face[0] == F_OUTFLOW) { if (dx == 0) return; if (dx == 1) sx = -1; }
+    if (vy == -1 && g.face[3] == F_OUTFLOW) { if (dy == g.ny - 1) return; if (dy == g.ny - 2) sy = 1; }
+    if (vy == 1 && g.face[2] == F_OUTFLOW) { if (dy == 0) return; if (dy == 1) sy = -1; }
+    if (vz == -1 && g.face[5] == F_OUTFLOW) { if (dz == g.nz - 1) return; if (dz == g.nz - 2) sz = 1; }
+    if (vz == 1 && g.face[4] == F_OUTFLOW) { if (dz == 0) return; if (dz == 1) sz = -1; }
+    if ((sx | sy | sz) == 0) return;
+    for (int sub = 1; sub < 8; sub++) {
+        if (((sub & 1) && !sx) || ((sub & 2) && !sy) || ((sub & 4) && !sz)) continue;
+        const int cx = dx + ((sub & 1) ? sx : 0);
+        const int cy = dy + ((sub & 2) ? sy : 0);
+        const int cz = dz + ((sub & 4) ? sz : 0);
+        if (!solid_at(mask, g, cx, cy, cz) && inflow_face_of(g, cx, cy, cz) < 0) dst[pop_index(L, J, cx, cy, cz)] = v;
+    }
+}
+
 // Every boundary rule, per cell: the step of one cell (x, y, z) in any mode.
 template <int K, int MODE, bool STATS>
 __device__ inline void general_cell(typename Codec<K>::store* dst, const typename Codec<K>::store* src,
@@ -56,8 +86,10 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
                 // canonical output of an inflow cell is its own equilibrium
                 dst[pop_index(ld, I, x, y, z)] = C::pack(h[I]);
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
-                if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0)
+                if (r.kind == 0 && !(r.x == x && r.y == y && r.z == z) && inflow_face_of(g, r.x, r.y, r.z) < 0) {
                     dst[pop_index(ld, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                    store_copies(dst, mask, g, ld, r.x, r.y, r.z, r.dir, r.vx, r.vy, r.vz, C::pack(h[opp(I)]));
+                }
             } else {
                 const Res r = resolve_plain<I>(g, mask, x, y, z);
                 if (r.kind == 0)
@@ -100,6 +132,8 @@ __device__ inline void general_cell(typename Codec<K>::store* dst, const typenam
                             if (inflow_face_of(g, r.x, r.y, r.z) >= 0) return;
                         }
                         dst[pop_index(ld, r.dir, r.x, r.y, r.z)] = C::pack(h[opp(I)]);
+                        if constexpr (MODE == MODE_PUSH)
+                            store_copies(dst, mask, g, ld, r.x, r.y, r.z, r.dir, r.vx, r.vy, r.vz, C::pack(h[opp(I)]));
                     }
                 }
             }

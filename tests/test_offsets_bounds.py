@@ -18,7 +18,7 @@ computation of the intended slot: the own slot I of the cell, and slot
 opp(I') of the pull source x - c' (c' = c_I with the components mirrored at
 the row's free-slip faces zeroed) whenever that source lies in the grid.
 Every address must also fall inside the population array.  The adjoint's
-outflow copies (one element further along x) and the push's inflow-cell
+and the push's outflow copies (one element further along x) and the push's inflow-cell
 store toward x = 1 are covered by the same enumeration, and the choice of
 rows per block (row_blocks) is checked against its statement for every ny
 up to 5000, and the multiply-high division that splits the step kernels'
@@ -73,8 +73,8 @@ struct Layout {
 };
 
 // Every address a kernel forms for the cells of the sampled rows: own slot,
-// pull source (with the row's free-slip mirrors), the adjoint's outflow
-// copy one element further along x.
+// pull source (with the row's free-slip mirrors), the push's and the
+// adjoint's outflow copy one element further along x.
 static void check(const Geo& g, const Layout& L, int e, bool adjoint)
 {
     const long long total = 19 * L.S * e;
@@ -122,9 +122,10 @@ static void check(const Geo& g, const Layout& L, int e, bool adjoint)
                 if (nb != want) fail("neighbour", g, e, cls, x, y, z, I, nb, want);
                 if (rowbase + O.odd[I] + (long long)off != want) fail("fast", g, e, cls, x, y, z, I, rowbase + O.odd[I] + off, want);
                 if (nb < 0 || nb + e > total) fail("neighbour-bounds", g, e, cls, x, y, z, I, nb, total);
-                if (adjoint && D[I][0] == 1 && x == g.nx - 1) {
+                if (!L.blocked && D[I][0] == 1 && x == g.nx - 1) {
+                    // push and adjoint: the outflow copy of the slot at nx - 2
                     const long long cp = rowbase + O.lo[I] + (long long)(uint32_t)(off + O.on[I] + (uint32_t)e);
-                    if (cp != want + e || cp + e > total) fail("adjoint-copy", g, e, cls, x, y, z, I, cp, want + e);
+                    if (cp != want + e || cp + e > total) fail("outflow-copy", g, e, cls, x, y, z, I, cp, want + e);
                 }
             }
         }
