@@ -216,7 +216,10 @@ def apply_feature(lat, name):
 
 
 def time_features(w, steps, warmup):
-    """FP32 step rate with each source or stabiliser switched on alone, and all together."""
+    """FP32 step rate with each source or stabiliser switched on alone, and
+    all together; and with the mean/RMS velocity statistics accumulated
+    every 10 steps (the long-run statistics of Sec. 2.3)."""
+    import torch
     out = {}
     for name in FEATURE_NAMES + ("all",):
         def setup(lat, name=name):
@@ -224,6 +227,12 @@ def time_features(w, steps, warmup):
                 apply_feature(lat, k)
         r = time_forward(w, "f32", steps, warmup, setup)
         out[name] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4)}
+    acc = torch.zeros(6, w.nz, w.ny, w.nx, dtype=torch.float32, device="cuda")
+    r = time_forward(w, "f32", steps, warmup, lambda lat: lat.set_stats(acc, 10))
+    out["stats_every_10_steps"] = {"value": round(r["mlups"], 1), "unit": "MLUPS",
+                                   "ms_per_step": round(r["ms_per_step"], 4)}
+    del acc
+    torch.cuda.empty_cache()
     return out
 
 
